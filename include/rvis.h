@@ -1,0 +1,282 @@
+/*
+ * rvis.h -- C ABI of the MI355X (gfx950) visibility tracer for 3D Gaussians.
+ *
+ * The library implements the point-based ray tracing of "Relightable 3D
+ * Gaussians" (arXiv 2311.16043), Sec. 4: a bounding volume hierarchy built as
+ * a binary radix tree over the Gaussians (Sec. 4.1, after Karras 2012), all-hit
+ * traversal that attenuates transmittance T by (1 - alpha_j) for every
+ * Gaussian a ray crosses (Sec. 4.1, Eq. (15)), with alpha_j the Gaussian's
+ * contribution at its equivalent intersection point (Eq. (13)-(14)), early
+ * termination below T_min, and per-Gaussian visibility pre-computation over N
+ * directions of the hemisphere about each normal (Sec. 4.2; directions from
+ * Fibonacci sampling, Sec. 3.3). Around that path: the adjoint of T with
+ * respect to opacity, mean and log-scale, and a small MLP visibility
+ * surrogate with tracer fallback.
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers (hipMalloc'd or torch-owned)
+ *    unless stated otherwise. Arrays are dense, row-major, FP32 unless stated.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Every call only
+ *    enqueues work on that stream and returns; nothing is synchronised. Inputs
+ *    must stay unchanged and alive until the stream has executed the call.
+ *  - The library never allocates device memory. Callers size buffers with the
+ *    *_bytes() queries and pass them in; the library owns nothing between calls.
+ *  - Every call validates its arguments before enqueuing anything and returns
+ *    an rv_status. On failure nothing has been enqueued (except RV_ERR_HIP,
+ *    reported after a failed launch) and rv_last_error() describes the cause.
+ *  - Ray ids: ray r = i * K + k is direction k of Gaussian i (original, not
+ *    sorted, order); ids are 64-bit.
+ */
+#ifndef RVIS_H
+#define RVIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rv_status;
+#define RV_OK 0
+#define RV_ERR_INVALID_ARG (-1)
+#define RV_ERR_WORKSPACE (-2)
+#define RV_ERR_HIP (-3)
+#define RV_ERR_UNSUPPORTED (-4)
+
+/* Largest Gaussian count the library accepts (node ids are 32-bit). */
+#define RV_MAX_GAUSSIANS (1LL << 30)
+
+/*
+ * The geometric part of the Gaussian set (Sec. 3.1: mean mu, unit quaternion
+ * q, scale s, opacity o; the normal n is the per-Gaussian attribute added in
+ * Sec. 3.3). Covariance Sigma = R(q) S S^T R(q)^T with S = diag(exp(log_scale)).
+ *   mean      [n][3]
+ *   quat      [n][4]  (w, x, y, z); normalised by the library before use
+ *   log_scale [n][3]
+ *   opacity   [n]
+ *   normal    [n][3]  unit normal (normalised before use); may be NULL when
+ *                     only sphere-mode directions are traced
+ */
+typedef struct rv_gaussians {
+    const float *mean;
+    const float *quat;
+    const float *log_scale;
+    const float *opacity;
+    const float *normal;
+    int64_t n;
+} rv_gaussians;
+
+/*
+ * Tracing parameters. A Gaussian j contributes to the ray leaving Gaussian i
+ * iff j != i, its peak parameter t_j >= t_min(i) = tmin_scale * max scale of i,
+ * its squared Mahalanobis distance at the peak q_j <= sigma_cut^2 and
+ * alpha_j = o_j exp(-q_j / 2) >= alpha_min; it then multiplies T by
+ * 1 - min(alpha_j, alpha_max). A ray stops once T < T_min (0 disables the
+ * early exit); the value returned is T at that point.
+ * dir_mode 0: directions are world-frame unit vectors (sphere).
+ * dir_mode 1: directions are local (x, y, z) with +z along the Gaussian's
+ *             normal (hemisphere), rotated by the Duff et al. 2017 basis.
+ * Defaults: {1/255, 0.99, 1e-4, 3, 3, 1}.
+ */
+typedef struct rv_trace_params {
+    float alpha_min;
+    float alpha_max;
+    float T_min;
+    float sigma_cut;
+    float tmin_scale;
+    int32_t dir_mode;
+} rv_trace_params;
+
+/* Device pointers into a built BVH blob (see rv_bvh_view). */
+typedef struct rv_bvh_arrays {
+    int64_t n;
+    const float *header;        /* [16]: lo[3], hi[3] of the means, root box lo[3], hi[3], ... */
+    const uint64_t *keys;       /* [n]   63-bit Morton keys, sorted ascending */
+    const uint32_t *perm;       /* [n]   sorted position -> original index */
+    const float *nodes;         /* [n-1][16] internal nodes, see below */
+    const int32_t *parent;      /* [2n-1] parent of internal node i at i, of leaf m at n-1+m; root -1 */
+    const float *leaf_records;  /* [n][16] per sorted leaf: mu[3], o, W row0[3], src, W row1[3], pad, W row2[3], pad */
+    const float *leaf_boxes;    /* [n][6]  per sorted leaf: lo[3], hi[3] (3-sigma box, widened outward) */
+    const float *origins;       /* [n][4]  per sorted leaf: unit normal[3], t_min */
+} rv_bvh_arrays;
+
+/* const char* describing the last failure on the calling thread ("" if none). */
+const char *rv_last_error(void);
+
+/* Library version string. */
+const char *rv_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* BVH build (Sec. 4.1)                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of the BVH blob for n Gaussians (256-byte aligned sections). */
+size_t rv_bvh_bytes(int64_t n);
+
+/* Bytes of build scratch for n Gaussians. */
+size_t rv_build_workspace_bytes(int64_t n);
+
+/*
+ * Build the LBVH of the Gaussian set g into `bvh` (rv_bvh_bytes(g->n) bytes,
+ * 256-byte aligned). Steps (all on `stream`): scene bounds of the means;
+ * 63-bit Morton keys (21 bits per axis, binary32 quantisation
+ * u = (x - lo) / (hi - lo), c = min(floor(u * 2^21), 2^21 - 1), x bits most
+ * significant in each triplet); stable LSD radix sort of (key, index);
+ * binary radix tree with Karras 2012 node numbering (internal node i has one
+ * end of its key range at i; the root is node 0; children are written as the
+ * internal id, or ~m for leaf m); per-leaf records in sorted order; bottom-up
+ * refit of the 3-sigma boxes. Node record (16 floats): left-child box lo[3],
+ * hi[3], right-child box lo[3], hi[3], then the left and right child ids as
+ * int32 bit patterns, then 2 unused words.
+ * The result depends only on the inputs (bit-identical across runs).
+ * Errors: RV_ERR_INVALID_ARG (null pointers, n < 1, n > RV_MAX_GAUSSIANS,
+ * unaligned bvh), RV_ERR_WORKSPACE (bvh_bytes or ws_bytes too small),
+ * RV_ERR_HIP (launch failure).
+ */
+rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_bytes, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/* Host-side decoding of a BVH blob into device pointers (no device access). */
+rv_status rv_bvh_view(const void *bvh, int64_t n, rv_bvh_arrays *out);
+
+/* ------------------------------------------------------------------------ */
+/* Visibility (Sec. 4.1 traversal, Sec. 4.2 pre-computation)                */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of trace scratch (persistent work counter, per-ray statistics). */
+size_t rv_trace_workspace_bytes(int64_t n, int32_t K);
+
+/*
+ * Trace all n*K rays: ray (i, k) starts at mean_i with direction k of `dirs`
+ * ([K][3], see dir_mode), after `bvh` was built from the same g. Writes
+ * vis_ray[i*K + k] = T of that ray (if vis_ray != NULL) and
+ * vis_mean[i] = (1/K) sum_k T (if vis_mean != NULL); at least one of them must
+ * be given. Deterministic (no atomics in the result).
+ * Errors: RV_ERR_INVALID_ARG (null g/bvh/dirs/params, K < 1, both outputs
+ * NULL, dir_mode 1 with NULL normals, out-of-range parameters),
+ * RV_ERR_WORKSPACE, RV_ERR_HIP.
+ */
+rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
+                              const rv_trace_params *p, float *vis_ray, float *vis_mean, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/*
+ * Trace an explicit list of ray ids (device int64 [n_rays], r = i*K + k) and
+ * write out[s] = T of ray ids[s]. Gives the same bits as rv_trace_visibility
+ * for the same ray.
+ */
+rv_status rv_trace_rays(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
+                        const rv_trace_params *p, const int64_t *ray_ids, int64_t n_rays, float *out,
+                        void *stream);
+
+/*
+ * Traversal statistics of rv_trace_visibility's rays: writes (device)
+ * totals[0] = internal nodes visited, totals[1] = leaf records tested,
+ * totals[2] = Gaussians included, summed over all n*K rays (int64, overwritten).
+ * Used to compute algorithmic bytes; runs a separate instrumented kernel.
+ */
+rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
+                         const rv_trace_params *p, int64_t *totals, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Gradient of L with respect to opacity [n], mean [n][3] and log_scale [n][3],
+ * given dL/dvis_ray [n*K] (or NULL) and dL/dvis_mean [n] (or NULL, at least one
+ * given). Each ray is traced again in the same order with the same early exit
+ * (no hit lists are stored): a first pass recovers the ray's final T (skipped
+ * when vis_ray_fwd, the forward's vis_ray, is given), a second pass adds, for
+ * every included Gaussian j with alpha_j < alpha_max,
+ *   dL/dalpha_j = -g * T / (1 - alpha_j),   g = dL/dT of the ray,
+ *   dalpha/do_j = alpha/o_j, dalpha/dmu_j = alpha W_j^T e,
+ *   dalpha/dlog_scale_{j,a} = alpha e_a^2, dalpha/dmu_i = -alpha W_j^T e,
+ * with W_j = diag(1/s_j) R_j^T and e = p + t* v the whitened closest-approach
+ * vector (dq/dt = 0 at the peak, so t* is not differentiated). Cuts and the
+ * clamp are not differentiated. Gradients are ACCUMULATED (+=) into the
+ * caller's buffers with FP32 atomics: zero them first; the summation order,
+ * hence the last bits, may vary between runs.
+ */
+rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
+                                       const rv_trace_params *p, const float *grad_vis_ray,
+                                       const float *grad_vis_mean, const float *vis_ray_fwd,
+                                       float *grad_opacity, float *grad_mean, float *grad_log_scale,
+                                       void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* MLP visibility surrogate                                                 */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Network: input x (3, normalised to [-1, 1] by the scene box lo/hi stored in
+ * the parameter blob) and unit direction d (3); each of the 6 scalars u is
+ * encoded as [u, sin(2^l pi u), cos(2^l pi u)] for l = 0, 1, 2 (42 features,
+ * zero-padded to 64); four hidden layers of 256 with ReLU (64->256, then
+ * 3 x 256->256); a 256->2 head giving V = sigmoid(z0) and the predicted
+ * absolute error u = softplus(z1). BF16 weights and activations into each
+ * matrix product, FP32 accumulation, FP32 master weights and Adam state.
+ */
+typedef struct rv_train_opts {
+    int64_t steps;      /* optimiser steps */
+    int32_t batch;      /* rows per step (multiple of 256) */
+    float lr;           /* Adam learning rate (peak) */
+    float beta1, beta2, eps;
+    float lr_min;       /* cosine decay floor */
+    uint64_t seed;      /* sample order */
+    int64_t step0;      /* global step of the first step (Adam bias correction, schedule) */
+    int64_t total_steps;/* schedule length */
+} rv_train_opts;
+
+/* Bytes of the surrogate parameter blob (FP32 master + Adam m, v + BF16 copies + box). */
+size_t rv_surrogate_bytes(void);
+
+/* Bytes of surrogate training scratch for a batch of `batch` rows. */
+size_t rv_surrogate_train_workspace_bytes(int32_t batch);
+
+/* Bytes of inference scratch for q_count queries. */
+size_t rv_surrogate_infer_workspace_bytes(int64_t q_count);
+
+/*
+ * Initialise the parameter blob: weights with a seeded He-uniform draw
+ * (counter-based hash of (seed, index)), biases 0, Adam state 0, and the
+ * normalisation box lo[3], hi[3] (host floats).
+ */
+rv_status rv_surrogate_init(void *params, uint64_t seed, const float *box_lo_host, const float *box_hi_host,
+                            void *stream);
+
+/*
+ * Train on n_samples tracer samples: x [n][3], d [n][3], T [n]. Each step takes
+ * `batch` sample indices from a seeded counter-based hash, runs the forward
+ * pass, the loss BCE(V, T) + L1(u, |T - V| with V held constant), the backward
+ * pass and one Adam step. loss_log [steps] (device, FP32; NULL to skip)
+ * receives the mean loss of each step.
+ */
+rv_status rv_surrogate_train(void *params, const float *x, const float *d, const float *T, int64_t n_samples,
+                             const rv_train_opts *o, float *loss_log, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* Free-form inference: vis[s], unc[s] (unc may be NULL) for n queries (x[s], d[s]). */
+rv_status rv_surrogate_infer_xd(const void *params, const float *x, const float *d, int64_t n, float *vis,
+                                float *unc, void *stream);
+
+/*
+ * Grid inference over queries q in [q_begin, q_begin + q_count) with q = i*K + k
+ * (x = mean_i, d = direction k of Gaussian i as in rv_trace_visibility).
+ * vis[s] receives the surrogate's V; where its predicted error exceeds tau and
+ * `bvh` is not NULL the query is traced instead (fallback) and vis[s] is the
+ * tracer's T. unc (may be NULL) receives the predicted error; *n_fallback
+ * (device int64) receives the number of traced queries.
+ */
+rv_status rv_surrogate_infer(const void *params, const void *bvh, const rv_gaussians *g, const float *dirs,
+                             int32_t K, const rv_trace_params *p, int64_t q_begin, int64_t q_count, float tau,
+                             float *vis, float *unc, int64_t *n_fallback, void *ws, size_t ws_bytes,
+                             void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RVIS_H */

@@ -1,0 +1,453 @@
+// build.hip -- LBVH construction over 3D Gaussians on gfx950 (Sec. 4.1: a
+// binary radix tree built after Karras 2012; leaves are the tight boxes of the
+// Gaussians, internal nodes the boxes of their two children).
+//
+// Pipeline on one stream, no host synchronisation:
+//   bounds_partial/bounds_final   min/max of the means (exact in any order)
+//   morton                        63-bit keys in binary32 arithmetic
+//   sort_hist/sort_scan/sort_scatter x 8   stable LSD radix sort, 8-bit digits,
+//                                 wave64 ballot ranking, one wave per tile
+//   leaf_prep                     per sorted leaf: whitening W, 3-sigma box, origin data
+//   karras                        internal nodes and parents, one thread per node
+//   fill_u32 + refit              bottom-up box union, second arrival continues
+#include "rv_internal.h"
+
+namespace rv {
+namespace {
+
+// Order-preserving float min/max in a block of 256 threads.
+__global__ __launch_bounds__(256) void k_bounds_partial(const float *__restrict__ mean, int64_t n,
+                                                        float *__restrict__ partial) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float x = mean[3 * i + a];
+            lo[a] = fminf(lo[a], x);
+            hi[a] = fmaxf(hi[a], x);
+        }
+    }
+    __shared__ float s[6][256];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = lo[a];
+        s[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + w]);
+                s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + w]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_bounds_final(const float *__restrict__ partial, int nparts,
+                                                      float *__restrict__ header, int64_t n) {
+    __shared__ float s[6][256];
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nparts; b += 256) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a] = fminf(v[a], partial[b * 6 + a]);
+            v[3 + a] = fmaxf(v[3 + a], partial[b * 6 + 3 + a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) s[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + w]);
+                s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + w]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) header[threadIdx.x] = s[threadIdx.x][0];
+    if (threadIdx.x == 6) header[12] = __int_as_float((int)(n & 0x7fffffff));
+}
+
+// Spread the low 21 bits of v to every third bit (bit b -> bit 3b).
+__device__ __forceinline__ uint64_t part1by2_21(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x001f00000000ffffull;
+    v = (v | (v << 16)) & 0x001f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+// Quantise one coordinate: every operation is a single correctly rounded
+// binary32 operation (sub, sub, div, exact scale by 2^21, floor, clamp).
+__device__ __forceinline__ uint32_t quantise21(float x, float lo, float hi) {
+#pragma clang fp contract(off)
+    float den = hi - lo;
+    float u = den > 0.0f ? (x - lo) / den : 0.0f;
+    float f = floorf(u * 2097152.0f);
+    f = fminf(fmaxf(f, 0.0f), 2097151.0f);
+    return (uint32_t)f;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const float *__restrict__ mean, int64_t n,
+                                                const float *__restrict__ header, uint64_t *__restrict__ keys,
+                                                uint32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t cx = quantise21(mean[3 * i + 0], header[0], header[3]);
+    uint32_t cy = quantise21(mean[3 * i + 1], header[1], header[4]);
+    uint32_t cz = quantise21(mean[3 * i + 2], header[2], header[5]);
+    keys[i] = (part1by2_21(cx) << 2) | (part1by2_21(cy) << 1) | part1by2_21(cz);
+    vals[i] = (uint32_t)i;
+}
+
+// ---- radix sort ------------------------------------------------------------
+
+__global__ __launch_bounds__(kSortWave) void k_sort_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                                         uint32_t *__restrict__ hist, int64_t nblocks) {
+    __shared__ uint32_t h[256];
+    const int lane = threadIdx.x;
+    for (int i = lane; i < 256; i += kSortWave) h[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int j = 0; j < kSortItems; ++j) {
+        int64_t idx = base + (int64_t)j * kSortWave + lane;
+        bool ok = idx < n;
+        uint32_t d = ok ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
+        uint64_t valid = __ballot(ok);
+        if (valid == 0) break;
+        uint64_t peers = match_digit8(d, valid);
+        // the lowest lane of each group adds the group's size
+        if (ok && (peers & ((1ull << lane) - 1ull)) == 0) h[d] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    for (int i = lane; i < 256; i += kSortWave) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
+}
+
+// Exclusive prefix sum over hist[256 * nblocks] (digit-major) in one block.
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ hist, int64_t total) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (total + 1023) / 1024;
+    const int64_t b = (int64_t)t * chunk, e = min(total, b + chunk);
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += hist[i];
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 1024 partial sums
+    for (int w = 1; w < 1024; w <<= 1) {
+        uint32_t v = (t >= w) ? part[t - w] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;  // exclusive
+    for (int64_t i = b; i < e; ++i) {
+        uint32_t v = hist[i];
+        hist[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kSortWave) void k_sort_scatter(const uint64_t *__restrict__ kin,
+                                                            const uint32_t *__restrict__ vin, int64_t n, int shift,
+                                                            const uint32_t *__restrict__ hist, int64_t nblocks,
+                                                            uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+    __shared__ uint32_t offs[256];
+    const int lane = threadIdx.x;
+    for (int i = lane; i < 256; i += kSortWave) offs[i] = hist[(int64_t)i * nblocks + blockIdx.x];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int j = 0; j < kSortItems; ++j) {
+        int64_t idx = base + (int64_t)j * kSortWave + lane;
+        bool ok = idx < n;
+        uint64_t key = ok ? kin[idx] : 0ull;
+        uint32_t val = ok ? vin[idx] : 0u;
+        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t valid = __ballot(ok);
+        if (valid == 0) break;
+        uint64_t peers = match_digit8(d, valid);
+        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        uint32_t pos = ok ? offs[d] + rank : 0u;
+        __builtin_amdgcn_wave_barrier();
+        // every lane has read its group's offset; the group leader advances it
+        if (ok && rank == 0) offs[d] = pos + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        if (ok) {
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+    }
+}
+
+// ---- leaf records ------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_leaf_prep(const float *__restrict__ mean, const float *__restrict__ quat,
+                                                   const float *__restrict__ log_scale,
+                                                   const float *__restrict__ opacity, const float *__restrict__ normal,
+                                                   int64_t n, const uint32_t *__restrict__ perm,
+                                                   float4 *__restrict__ rec, float *__restrict__ box,
+                                                   float4 *__restrict__ origins) {
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int64_t i = perm[m];
+    float qw = quat[4 * i], qx = quat[4 * i + 1], qy = quat[4 * i + 2], qz = quat[4 * i + 3];
+    float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+    // rotation matrix of the unit quaternion (w, x, y, z)
+    float R[3][3];
+    R[0][0] = 1.f - 2.f * (qy * qy + qz * qz); R[0][1] = 2.f * (qx * qy - qw * qz); R[0][2] = 2.f * (qx * qz + qw * qy);
+    R[1][0] = 2.f * (qx * qy + qw * qz); R[1][1] = 1.f - 2.f * (qx * qx + qz * qz); R[1][2] = 2.f * (qy * qz - qw * qx);
+    R[2][0] = 2.f * (qx * qz - qw * qy); R[2][1] = 2.f * (qy * qz + qw * qx); R[2][2] = 1.f - 2.f * (qx * qx + qy * qy);
+    float ls[3] = {log_scale[3 * i], log_scale[3 * i + 1], log_scale[3 * i + 2]};
+    float s[3], is[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s[a] = expf(ls[a]);
+        is[a] = expf(-ls[a]);
+    }
+    float mu[3] = {mean[3 * i], mean[3 * i + 1], mean[3 * i + 2]};
+    // whitening W = diag(1/s) R^T: row a is column a of R divided by s_a
+    float W[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) W[a][c] = is[a] * R[c][a];
+    rec[4 * m + 0] = make_float4(mu[0], mu[1], mu[2], opacity[i]);
+    rec[4 * m + 1] = make_float4(W[0][0], W[0][1], W[0][2], __int_as_float((int)i));
+    rec[4 * m + 2] = make_float4(W[1][0], W[1][1], W[1][2], 0.0f);
+    rec[4 * m + 3] = make_float4(W[2][0], W[2][1], W[2][2], 0.0f);
+    // 3-sigma box: half extent along world axis a is 3 sqrt(sum_m (R_am s_m)^2),
+    // widened by a relative 2^-12 and by ~4 ulp of the coordinate so that a
+    // rounded box never cuts into the support
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float e0 = R[a][0] * s[0], e1 = R[a][1] * s[1], e2 = R[a][2] * s[2];
+        float h = kBuildSigma * sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+        h = h * (1.0f + 0x1p-12f) + fabsf(mu[a]) * 0x1p-21f + 0x1p-126f;
+        box[6 * m + a] = mu[a] - h;
+        box[6 * m + 3 + a] = mu[a] + h;
+    }
+    float nx = 0.f, ny = 0.f, nz = 1.f;
+    if (normal) {
+        nx = normal[3 * i]; ny = normal[3 * i + 1]; nz = normal[3 * i + 2];
+        float nl = sqrtf(nx * nx + ny * ny + nz * nz);
+        nx /= nl; ny /= nl; nz /= nl;
+    }
+    float smax = expf(fmaxf(ls[0], fmaxf(ls[1], ls[2])));
+    origins[m] = make_float4(nx, ny, nz, smax);
+}
+
+// ---- Karras internal nodes ---------------------------------------------------
+
+// Common-prefix length of the augmented keys (key, position) at i and j;
+// -1 when j is outside [0, n).
+__device__ __forceinline__ int prefix_len(const uint64_t *__restrict__ k, int64_t n, int64_t i, int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    uint64_t a = k[i], b = k[j];
+    if (a != b) return __clzll((long long)(a ^ b));
+    return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+}
+
+__global__ __launch_bounds__(256) void k_karras(const uint64_t *__restrict__ keys, int64_t n,
+                                                float4 *__restrict__ nodes, int32_t *__restrict__ parent) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    // direction of the range: towards the neighbour sharing the longer prefix
+    const int d = (prefix_len(keys, n, i, i + 1) - prefix_len(keys, n, i, i - 1)) > 0 ? 1 : -1;
+    const int dmin = prefix_len(keys, n, i, i - d);
+    // exponential search for an upper bound of the range length, then binary search
+    int64_t lmax = 2;
+    while (prefix_len(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (prefix_len(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    const int64_t j = i + l * d;
+    const int dnode = prefix_len(keys, n, i, j);
+    // split: the last position (counted from i) sharing more than dnode bits with i
+    int64_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (prefix_len(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    const int32_t left = (lo == gamma) ? ~(int32_t)gamma : (int32_t)gamma;
+    const int32_t right = (hi == gamma + 1) ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
+    nodes[4 * i + 3] = make_float4(__int_as_float(left), __int_as_float(right), 0.0f, 0.0f);
+    parent[left >= 0 ? left : (n - 1 + (int64_t)~left)] = (int32_t)i;
+    parent[right >= 0 ? right : (n - 1 + (int64_t)~right)] = (int32_t)i;
+    if (i == 0) parent[0] = -1;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, int64_t count, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// ---- bottom-up refit -----------------------------------------------------------
+
+// Box of a child: a leaf's own box, or the union of an internal node's two
+// child slots (left: floats 0-5, right: floats 6-11 of its record).
+__device__ __forceinline__ void child_box(int32_t child, const float *__restrict__ leaf_box, const float *nodes,
+                                          float b[6]) {
+    if (child < 0) {
+        const float *lb = leaf_box + 6 * (int64_t)~child;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) b[a] = lb[a];
+    } else {
+        const float *rec = nodes + 16 * (int64_t)child;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float l0 = __hip_atomic_load(rec + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const float l1 = __hip_atomic_load(rec + 6 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const float h0 = __hip_atomic_load(rec + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const float h1 = __hip_atomic_load(rec + 9 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            b[a] = fminf(l0, l1);
+            b[3 + a] = fmaxf(h0, h1);
+        }
+    }
+}
+
+// One thread per leaf walks towards the root. At each parent it stores its
+// child's box into the parent's record and bumps the parent's counter; the
+// first arrival stops, the second (which then sees both slots) continues.
+// Only node ids are carried from level to level; each level re-reads the
+// box it publishes.
+__global__ __launch_bounds__(256) void k_refit(int64_t n, const float *__restrict__ leaf_box,
+                                               const int32_t *__restrict__ parent, float *nodes,
+                                               uint32_t *flags, float *header) {
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    int32_t child = ~(int32_t)m;
+    int32_t node = parent[n - 1 + m];
+    // a valid tree has at most 95 internal levels; the bound only guards the loop
+    for (int level = 0; node >= 0 && level < 128; ++level) {
+        float b[6];
+        child_box(child, leaf_box, nodes, b);
+        float *rec = nodes + 16 * (int64_t)node;
+        const int32_t lc = __float_as_int(rec[12]);
+        float *slot = rec + (lc == child ? 0 : 6);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) slot[a] = b[a];
+        // release our box, acquire the sibling's: device scope (all XCDs)
+        const uint32_t prev = __hip_atomic_fetch_add(flags + node, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == 0) return;  // first arrival: the sibling's thread continues
+        child = node;
+        node = parent[node];
+    }
+    if (node < 0) {
+        float b[6];
+        child_box(child, leaf_box, nodes, b);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) header[6 + a] = b[a];
+    }
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+}  // namespace rv
+
+using namespace rv;
+
+extern "C" size_t rv_bvh_bytes(int64_t n) { return n < 1 ? 0 : bvh_layout(n).total; }
+
+extern "C" size_t rv_build_workspace_bytes(int64_t n) { return n < 1 ? 0 : build_ws_layout(n).total; }
+
+extern "C" rv_status rv_bvh_view(const void *bvh, int64_t n, rv_bvh_arrays *out) {
+    clear_error();
+    RV_REQUIRE(bvh && out, RV_ERR_INVALID_ARG, "rv_bvh_view: null pointer");
+    RV_REQUIRE(n >= 1 && n <= RV_MAX_GAUSSIANS, RV_ERR_INVALID_ARG, "rv_bvh_view: n out of range");
+    BvhLayout L = bvh_layout(n);
+    out->n = n;
+    out->header = at<float>(bvh, L.header);
+    out->keys = at<uint64_t>(bvh, L.keys);
+    out->perm = at<uint32_t>(bvh, L.perm);
+    out->nodes = at<float>(bvh, L.nodes);
+    out->parent = at<int32_t>(bvh, L.parent);
+    out->leaf_records = at<float>(bvh, L.leaf_rec);
+    out->leaf_boxes = at<float>(bvh, L.leaf_box);
+    out->origins = at<float>(bvh, L.origins);
+    return RV_OK;
+}
+
+extern "C" rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_bytes, void *ws, size_t ws_bytes,
+                                  void *stream) {
+    clear_error();
+    RV_REQUIRE(g && bvh && ws, RV_ERR_INVALID_ARG, "rv_build_bvh: null argument (g, bvh or ws)");
+    RV_REQUIRE(g->mean && g->quat && g->log_scale && g->opacity, RV_ERR_INVALID_ARG,
+               "rv_build_bvh: null Gaussian array");
+    const int64_t n = g->n;
+    RV_REQUIRE(n >= 1 && n <= RV_MAX_GAUSSIANS, RV_ERR_INVALID_ARG, "rv_build_bvh: n=%lld out of range",
+               (long long)n);
+    RV_REQUIRE(((uintptr_t)bvh % kAlign) == 0 && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG,
+               "rv_build_bvh: bvh and ws must be 256-byte aligned");
+    const BvhLayout L = bvh_layout(n);
+    const BuildWsLayout W = build_ws_layout(n);
+    RV_REQUIRE(bvh_bytes >= L.total, RV_ERR_WORKSPACE, "rv_build_bvh: bvh_bytes %zu < %zu", bvh_bytes, L.total);
+    RV_REQUIRE(ws_bytes >= W.total, RV_ERR_WORKSPACE, "rv_build_bvh: ws_bytes %zu < %zu", ws_bytes, W.total);
+    hipStream_t s = (hipStream_t)stream;
+
+    float *header = at<float>(bvh, L.header);
+    uint64_t *keys = at<uint64_t>(bvh, L.keys);
+    uint32_t *perm = at<uint32_t>(bvh, L.perm);
+    float *nodes = at<float>(bvh, L.nodes);
+    int32_t *parent = at<int32_t>(bvh, L.parent);
+    float4 *rec = at<float4>(bvh, L.leaf_rec);
+    float *box = at<float>(bvh, L.leaf_box);
+    float4 *orig = at<float4>(bvh, L.origins);
+    uint64_t *keys_tmp = at<uint64_t>(ws, W.keys_tmp);
+    uint32_t *vals_tmp = at<uint32_t>(ws, W.vals_tmp);
+    uint32_t *hist = at<uint32_t>(ws, W.hist);
+    float *bpart = at<float>(ws, W.bounds);
+    uint32_t *flags = at<uint32_t>(ws, W.flags);
+
+    const int nb = (int)std::min<int64_t>(kBoundsBlocks, (n + 255) / 256);
+    hipLaunchKernelGGL(k_bounds_partial, dim3(nb), dim3(256), 0, s, g->mean, n, bpart);
+    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, bpart, nb, header, n);
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, 256)), dim3(256), 0, s, g->mean, n, header, keys, perm);
+    rv_status st = check_launch("morton");
+    if (st != RV_OK) return st;
+
+    // 8 passes of 8 bits; even count, so the result lands back in keys/perm
+    uint64_t *ka = keys, *kb = keys_tmp;
+    uint32_t *va = perm, *vb = vals_tmp;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)W.nblocks), dim3(kSortWave), 0, s, ka, n, shift, hist,
+                           W.nblocks);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * W.nblocks);
+        hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)W.nblocks), dim3(kSortWave), 0, s, ka, va, n, shift,
+                           hist, W.nblocks, kb, vb);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    st = check_launch("radix sort");
+    if (st != RV_OK) return st;
+
+    hipLaunchKernelGGL(k_leaf_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, g->mean, g->quat, g->log_scale,
+                       g->opacity, g->normal, n, perm, rec, box, orig);
+    if (n > 1) {
+        hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, keys, n,
+                           reinterpret_cast<float4 *>(nodes), parent);
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, flags, n - 1, 0u);
+        hipLaunchKernelGGL(k_refit, dim3(grid_for(n, 256)), dim3(256), 0, s, n, box, parent, nodes, flags, header);
+    } else {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(parent), (int64_t)1,
+                           0xffffffffu);
+        hipLaunchKernelGGL(k_refit, dim3(1), dim3(64), 0, s, n, box, parent, nodes, flags, header);
+    }
+    return check_launch("leaf records / karras / refit");
+}

@@ -1,0 +1,236 @@
+// trace_core.h -- per-lane all-hit BVH traversal of one ray through 3D
+// Gaussians (Sec. 4.1): starting at the root, test both children's boxes,
+// descend into the hit ones, and at each leaf evaluate the Gaussian at its
+// equivalent intersection point (Eq. (13), peak parameter Eq. (14) with
+// Sigma^-1) and attenuate T by (1 - alpha) (Eq. (15)); stop early once
+// T < T_min. The order of hits does not matter for T (Sec. 4.1), so children
+// are visited left first without sorting by distance.
+#pragma once
+
+#include "rv_internal.h"
+
+namespace rv {
+
+// Deepest possible root-to-leaf path: each level consumes at least one bit of
+// the 95-bit augmented key (63-bit Morton key + 32-bit position).
+constexpr int kMaxDepth = 96;
+
+struct Cuts {
+    float alpha_min, alpha_max, T_stop, q_cut, tmin_scale;
+    int dir_mode;
+};
+
+inline Cuts make_cuts(const rv_trace_params &p) {
+    Cuts c;
+    c.alpha_min = p.alpha_min;
+    c.alpha_max = p.alpha_max;
+    c.T_stop = p.T_min;
+    c.q_cut = p.sigma_cut * p.sigma_cut;
+    c.tmin_scale = p.tmin_scale;
+    c.dir_mode = p.dir_mode;
+    return c;
+}
+
+// Orthonormal basis (b1, b2) completing the unit normal n: Duff et al.,
+// "Building an Orthonormal Basis, Revisited" (JCGT 2017).
+__device__ __forceinline__ void onb_duff(f3 n, f3 &b1, f3 &b2) {
+    const float sign = copysignf(1.0f, n.z);
+    const float a = -1.0f / (sign + n.z);
+    const float b = n.x * n.y * a;
+    b1 = mk(1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x);
+    b2 = mk(b, sign + n.y * n.y * a, -n.y);
+}
+
+// Direction k: world frame (mode 0) or local frame about n (mode 1), unit length.
+__device__ __forceinline__ f3 ray_direction(const float *__restrict__ dirs, int k, int mode, f3 n, f3 b1, f3 b2) {
+    const float dx = dirs[3 * k], dy = dirs[3 * k + 1], dz = dirs[3 * k + 2];
+    f3 d = mode ? (dx * b1 + dy * b2 + dz * n) : mk(dx, dy, dz);
+    const float inv = 1.0f / sqrtf(dot(d, d));
+    return inv * d;
+}
+
+// Reciprocal direction with zero components replaced by a tiny signed value.
+__device__ __forceinline__ f3 safe_inv(f3 d) {
+    auto r = [](float x) {
+        const float tiny = 1e-30f;
+        float y = fabsf(x) < tiny ? copysignf(tiny, x) : x;
+        return 1.0f / y;
+    };
+    return mk(r(d.x), r(d.y), r(d.z));
+}
+
+// Conservative slab test of the ray segment [t0, inf) against a box: the
+// differences are taken before scaling and the exit distance is enlarged by
+// (1 + 2 gamma_3) (Ize, "Robust BVH Ray Traversal", JCGT 2013), so a box the
+// exact ray enters is never rejected by rounding.
+__device__ __forceinline__ bool slab_hit(float lx, float ly, float lz, float hx, float hy, float hz, f3 o, f3 inv,
+                                         float t0) {
+    const float ax = (lx - o.x) * inv.x, bx = (hx - o.x) * inv.x;
+    const float ay = (ly - o.y) * inv.y, by = (hy - o.y) * inv.y;
+    const float az = (lz - o.z) * inv.z, bz = (hz - o.z) * inv.z;
+    const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t0));
+    const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+    return tn <= tf * 1.0000004f;
+}
+
+// What a leaf test hands to a hit callback.
+struct LeafHit {
+    float alpha;     // unclamped alpha = o exp(-q/2)
+    bool clamped;    // alpha >= alpha_max (contribution used min(alpha, alpha_max))
+    float opacity;
+    int32_t src;     // original index of the Gaussian
+    f3 e;            // whitened closest-approach vector p + t* v (|e|^2 = q)
+    f3 w0, w1, w2;   // rows of W
+};
+
+struct NoHit {
+    __device__ __forceinline__ void operator()(const LeafHit &, float) const {}
+};
+
+// Evaluate leaf m for the ray (o, d) of source `self`. Returns the factor
+// (1 - alpha) to multiply into T (1 when excluded); calls on_hit for included
+// Gaussians with the running T before this factor.
+template <class OnHit>
+__device__ __forceinline__ float leaf_factor(const float4 *__restrict__ rec, int32_t m, f3 o, f3 d, float tmin,
+                                             int32_t self, const Cuts &c, OnHit &on_hit, float T_before) {
+    const float4 r1 = rec[4 * m + 1];
+    const int32_t src = __float_as_int(r1.w);
+    if (src == self) return 1.0f;
+    const float4 r0 = rec[4 * m + 0];
+    const float4 r2 = rec[4 * m + 2];
+    const float4 r3 = rec[4 * m + 3];
+    const f3 w0 = mk(r1.x, r1.y, r1.z), w1 = mk(r2.x, r2.y, r2.z), w2 = mk(r3.x, r3.y, r3.z);
+    const f3 x = o - mk(r0.x, r0.y, r0.z);
+    const f3 p = mk(dot(w0, x), dot(w1, x), dot(w2, x));
+    const f3 v = mk(dot(w0, d), dot(w1, d), dot(w2, d));
+    const float vv = dot(v, v);
+    const float pv = dot(p, v);
+    const float inv_vv = 1.0f / vv;
+    const float t = -pv * inv_vv;
+    if (!(t >= tmin)) return 1.0f;
+    const f3 cp = cross(p, v);
+    const float q = dot(cp, cp) * inv_vv;
+    if (!(q <= c.q_cut)) return 1.0f;
+    const float alpha = r0.w * __expf(-0.5f * q);
+    if (!(alpha >= c.alpha_min)) return 1.0f;
+    const float ac = fminf(alpha, c.alpha_max);
+    LeafHit h;
+    h.alpha = alpha;
+    h.clamped = alpha >= c.alpha_max;
+    h.opacity = r0.w;
+    h.src = src;
+    h.e = p + t * v;
+    h.w0 = w0;
+    h.w1 = w1;
+    h.w2 = w2;
+    on_hit(h, T_before);
+    return 1.0f - ac;
+}
+
+// LDS ring holding the top kRing stack entries of each lane (slot-major, so a
+// wave's lanes touch consecutive words for equal depths); deeper entries spill
+// to a private array. Invariant: entries [max(0, sp - kRing), sp) live in the
+// ring at slot (index % kRing), entries [0, sp - kRing) in spill[].
+template <int kRing>
+struct RingStack {
+    int32_t *lds;   // this lane's column: lds[slot * stride]
+    int stride;
+    int sp;
+    int32_t spill[kMaxDepth - kRing];
+
+    __device__ __forceinline__ void reset() { sp = 0; }
+    __device__ __forceinline__ bool empty() const { return sp == 0; }
+    __device__ __forceinline__ bool full() const { return sp >= kMaxDepth; }
+    __device__ __forceinline__ void push(int32_t x) {
+        const int slot = sp & (kRing - 1);
+        if (sp >= kRing) spill[sp - kRing] = lds[slot * stride];
+        lds[slot * stride] = x;
+        ++sp;
+    }
+    __device__ __forceinline__ int32_t pop() {
+        --sp;
+        const int slot = sp & (kRing - 1);
+        const int32_t x = lds[slot * stride];
+        if (sp >= kRing) lds[slot * stride] = spill[sp - kRing];
+        return x;
+    }
+};
+
+// One ray's traversal state; step() processes one internal node.
+template <int kRing>
+struct RayState {
+    f3 o, d, inv;
+    float tmin, T;
+    int32_t self;
+    int32_t node;   // next internal node to visit, -1 when finished
+    int64_t budget; // steps left: a ray visits each of the n-1 internal nodes at most once
+    RingStack<kRing> st;
+
+    __device__ __forceinline__ void start(f3 o_, f3 d_, float tmin_, int32_t self_, int64_t n) {
+        o = o_;
+        d = d_;
+        inv = safe_inv(d_);
+        tmin = tmin_;
+        self = self_;
+        T = 1.0f;
+        st.reset();
+        node = n > 1 ? 0 : -1;   // a single Gaussian is the source itself
+        budget = n;
+    }
+
+    // A malformed tree (never produced by the builder) ends the ray with NaN
+    // instead of looping or overflowing the stack.
+    __device__ __forceinline__ bool fail() {
+        node = -1;
+        T = __int_as_float(0x7fc00000);
+        return true;
+    }
+
+    // Visit `node`; returns true when the ray is finished.
+    template <class OnHit, bool kCount = false>
+    __device__ __forceinline__ bool step(const float4 *__restrict__ nodes, const float4 *__restrict__ rec,
+                                         const Cuts &c, OnHit &on_hit, int64_t *n_nodes = nullptr,
+                                         int64_t *n_leaves = nullptr, int64_t *n_hits = nullptr) {
+        if (--budget < 0) return fail();
+        const float4 a = nodes[4 * node + 0];
+        const float4 b = nodes[4 * node + 1];
+        const float4 cc = nodes[4 * node + 2];
+        const float4 ids = nodes[4 * node + 3];
+        const int32_t left = __float_as_int(ids.x), right = __float_as_int(ids.y);
+        const bool hl = slab_hit(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, tmin);
+        const bool hr = slab_hit(b.z, b.w, cc.x, cc.y, cc.z, cc.w, o, inv, tmin);
+        if (kCount) ++*n_nodes;
+        if (hl && left < 0) {
+            const float f = leaf_factor(rec, ~left, o, d, tmin, self, c, on_hit, T);
+            if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
+            T *= f;
+        }
+        if (hr && right < 0) {
+            const float f = leaf_factor(rec, ~right, o, d, tmin, self, c, on_hit, T);
+            if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
+            T *= f;
+        }
+        if (T < c.T_stop) {
+            node = -1;
+            return true;
+        }
+        const bool gl = hl && left >= 0, gr = hr && right >= 0;
+        if (gl && gr) {
+            if (st.full()) return fail();
+            st.push(right);
+            node = left;
+        } else if (gl) {
+            node = left;
+        } else if (gr) {
+            node = right;
+        } else if (!st.empty()) {
+            node = st.pop();
+        } else {
+            node = -1;
+            return true;
+        }
+        return false;
+    }
+};
+
+}  // namespace rv

@@ -1,0 +1,125 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, answers size queries, and rejects invalid arguments before touching
+the device (these calls never launch anything, so they run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2311_16043_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2311_16043_amd import build
+        build.build(verbose=False)
+    return _lib.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rvis.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rv_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(_lib.SIGNATURES), "binding signatures must cover the header exactly"
+
+
+def test_version_and_empty_error(lib):
+    assert b"gfx950" in lib.rv_version()
+
+
+def test_size_queries(lib):
+    assert lib.rv_bvh_bytes(0) == 0
+    prev = 0
+    for n in (1, 2, 1000, 300_000, 3_000_000):
+        b = lib.rv_bvh_bytes(n)
+        assert b % 256 == 0 and b >= prev
+        # at least keys, perm, nodes, leaf records
+        assert b >= n * (8 + 4 + 64) + (n - 1) * 64
+        prev = b
+        assert lib.rv_build_workspace_bytes(n) >= n * 12
+
+
+def test_bvh_view_offsets_are_aligned_and_ordered(lib):
+    base = 1 << 40  # never dereferenced
+    out = _lib.RvBvhArrays()
+    assert lib.rv_bvh_view(base, 1000, C.byref(out)) == 0
+    ptrs = [out.header, out.keys, out.perm, out.nodes, out.parent, out.leaf_records, out.leaf_boxes, out.origins]
+    assert all(p % 256 == 0 for p in ptrs)
+    assert ptrs == sorted(ptrs) and ptrs[0] == base
+    assert ptrs[-1] + 1000 * 16 <= base + lib.rv_bvh_bytes(1000)
+    assert lib.rv_bvh_view(None, 10, C.byref(out)) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_bvh_view(base, 0, C.byref(out)) == _lib.RV_ERR_INVALID_ARG
+
+
+def _g(n=10, ptr=1 << 40, normal=True):
+    return _lib.RvGaussians(ptr, ptr, ptr, ptr, ptr if normal else None, n)
+
+
+def test_build_rejects_bad_arguments(lib):
+    g = _g()
+    ok_bytes = lib.rv_bvh_bytes(10)
+    ws = lib.rv_build_workspace_bytes(10)
+    P = 1 << 40
+    assert lib.rv_build_bvh(None, P, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert b"null" in lib.rv_last_error()
+    assert lib.rv_build_bvh(C.byref(_g(0)), P, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_build_bvh(C.byref(_g(1 << 31)), P, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_build_bvh(C.byref(g), P + 4, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_build_bvh(C.byref(g), P, ok_bytes - 256, P, ws, None) == _lib.RV_ERR_WORKSPACE
+    assert lib.rv_build_bvh(C.byref(g), P, ok_bytes, P, ws - 256, None) == _lib.RV_ERR_WORKSPACE
+    bad = _g()
+    bad.quat = None
+    assert lib.rv_build_bvh(C.byref(bad), P, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+
+
+def _params(**kw):
+    p = dict(alpha_min=1 / 255, alpha_max=0.99, T_min=1e-4, sigma_cut=3.0, tmin_scale=3.0, dir_mode=1)
+    p.update(kw)
+    return _lib.RvTraceParams(**p)
+
+
+@pytest.mark.parametrize("bad", [dict(dir_mode=2), dict(sigma_cut=3.5), dict(sigma_cut=0.0), dict(alpha_max=1.0),
+                                 dict(alpha_min=0.0), dict(T_min=-1.0), dict(T_min=1.0), dict(alpha_min=0.995)])
+def test_trace_rejects_bad_params(lib, bad):
+    P = 1 << 40
+    g = _g()
+    p = _params(**bad)
+    assert lib.rv_trace_visibility(P, C.byref(g), P, 8, C.byref(p), P, P, None, 0, None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_last_error()
+
+
+def test_trace_rejects_bad_arguments(lib):
+    P = 1 << 40
+    g = _g()
+    p = _params()
+    f = lib.rv_trace_visibility
+    assert f(P, C.byref(g), P, 0, C.byref(p), P, P, None, 0, None) == _lib.RV_ERR_INVALID_ARG  # K = 0
+    assert f(P, C.byref(g), P, 8, C.byref(p), None, None, None, 0, None) == _lib.RV_ERR_INVALID_ARG  # no output
+    assert f(None, C.byref(g), P, 8, C.byref(p), P, P, None, 0, None) == _lib.RV_ERR_INVALID_ARG
+    gn = _g(normal=False)
+    assert f(P, C.byref(gn), P, 8, C.byref(p), P, P, None, 0, None) == _lib.RV_ERR_INVALID_ARG  # hemisphere, no normal
+    assert lib.rv_trace_rays(P, C.byref(g), P, 8, C.byref(p), P, -1, P, None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_trace_rays(P, C.byref(g), P, 8, C.byref(p), None, 0, None, None) == 0  # empty list: no-op
+    assert lib.rv_trace_visibility_backward(P, C.byref(g), P, 8, C.byref(p), None, None, None, P, P, P,
+                                            None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_trace_visibility_backward(P, C.byref(g), P, 8, C.byref(p), P, None, None, None, P, P,
+                                            None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_trace_stats(P, C.byref(g), P, 8, C.byref(p), None, None, 0, None) == _lib.RV_ERR_INVALID_ARG
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.load()

@@ -1,0 +1,117 @@
+"""GPU LBVH build vs the oracle: Morton keys, sort order and radix-tree topology
+bit-exact; leaf boxes conservative and tight against the FP64 3-sigma boxes;
+internal boxes the exact union of their children; repeated builds identical."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2311_16043_amd import Gaussians, build_bvh
+from workloads import scenes
+
+from _parity import oracle_lbvh
+
+pytestmark = pytest.mark.gpu
+
+
+def _build(scene):
+    g = Gaussians.from_scene(scene)
+    bvh = build_bvh(g)
+    torch.cuda.synchronize()
+    return g, bvh, bvh.arrays()
+
+
+def check_build(scene, label=""):
+    n = scene["mean"].shape[0]
+    print(f"[build {label}] n={n}", flush=True)
+    g, bvh, A = _build(scene)
+    O = oracle_lbvh(scene)
+    assert np.array_equal(A["header"][0:3], O["lo"]) and np.array_equal(A["header"][3:6], O["hi"])
+    assert np.array_equal(A["keys"], O["keys"][O["order"]]), "sorted Morton keys differ"
+    assert np.array_equal(A["perm"].astype(np.int64), O["order"]), "sort permutation differs"
+    if n > 1:
+        assert np.array_equal(A["left"], O["left"]), "left children differ"
+        assert np.array_equal(A["right"], O["right"]), "right children differ"
+    assert np.array_equal(A["parent"], O["parent"]), "parents differ"
+    # leaf records carry the source index and opacity in sorted order
+    rec = A["leaf_records"]
+    assert np.array_equal(rec[:, 7].view(np.int32).astype(np.int64), O["order"])
+    assert np.array_equal(rec[:, 3], scene["opacity"][O["order"]])
+    assert np.array_equal(rec[:, 0:3], scene["mean"][O["order"]])
+    # leaf boxes: contain the FP64 3-sigma box, and are tight
+    llo, lhi = oracle.leaf_boxes(scene)
+    olo, ohi = llo[O["order"]], lhi[O["order"]]
+    glo = A["leaf_boxes"][:, 0:3].astype(np.float64)
+    ghi = A["leaf_boxes"][:, 3:6].astype(np.float64)
+    assert np.all(glo <= olo) and np.all(ghi >= ohi), "a leaf box cuts into the 3-sigma support"
+    slack = 0.5 * (ohi - olo) * 1e-3 + 1e-6 * np.maximum(1.0, np.abs(olo))
+    assert np.all(olo - glo <= slack) and np.all(ghi - ohi <= slack), "leaf boxes not tight"
+    if n > 1:
+        # every child slot holds the child's own box: the leaf box, or the union
+        # of the internal child's two slots (exact min/max)
+        lb, rb = A["left_box"], A["right_box"]
+        node_box = np.concatenate([np.minimum(lb[:, 0:3], rb[:, 0:3]), np.maximum(lb[:, 3:6], rb[:, 3:6])], 1)
+        for slot, ch in ((lb, A["left"]), (rb, A["right"])):
+            leaf = ch < 0
+            assert np.array_equal(slot[leaf], A["leaf_boxes"][~ch[leaf]])
+            assert np.array_equal(slot[~leaf], node_box[ch[~leaf]])
+        root = node_box[0]
+    else:
+        root = A["leaf_boxes"][0]
+    allb = np.concatenate([A["leaf_boxes"][:, 0:3].min(0), A["leaf_boxes"][:, 3:6].max(0)])
+    assert np.array_equal(root, allb) and np.array_equal(A["header"][6:12], allb)
+    return g, bvh, A
+
+
+def test_build_tiny_full():
+    check_build(scenes.make_scene("tiny"), "tiny")
+
+
+def test_build_object_small_and_ragged():
+    check_build(scenes.make_object_scene(20_001, 1), "object-20001")
+
+
+def test_build_multi_small():
+    check_build(scenes.make_multi_object_scene(4, 5_000, 2), "multi-4x5000")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 2047, 2048, 2049])
+def test_build_edge_sizes(n):
+    check_build(scenes.make_cube_cloud(n, 0), f"cube-{n}")
+
+
+def test_build_duplicate_means_use_position_tiebreak():
+    sc = scenes.make_cube_cloud(300, 0)
+    sc["mean"][:] = sc["mean"][17]          # all keys equal
+    check_build(sc, "all-equal")
+    sc = scenes.make_cube_cloud(500, 0)
+    sc["mean"][::2] = sc["mean"][1]         # half of them equal
+    check_build(sc, "half-equal")
+
+
+def test_build_planar_scene_zero_extent_axis():
+    sc = scenes.make_cube_cloud(1000, 0)
+    sc["mean"][:, 2] = np.float32(0.25)
+    check_build(sc, "planar")
+
+
+def test_build_is_deterministic():
+    sc = scenes.make_object_scene(50_000, 1)
+    _, _, A = _build(sc)
+    for _ in range(4):
+        _, _, B = _build(sc)
+        for k in A:
+            assert np.array_equal(A[k].view(np.uint8), B[k].view(np.uint8)), k
+
+
+def test_build_object_scale_full_size():
+    """Object-scale scene at its full 300,000 Gaussians."""
+    check_build(scenes.make_scene("object"), "object-300k")
+
+
+def test_build_multi_object_full_size():
+    """Multi-object composition at its full 1.2M Gaussians: Morton, sort and
+    topology bit-exact."""
+    check_build(scenes.make_scene("multi"), "multi-1.2M")

@@ -1,0 +1,163 @@
+"""GPU visibility vs the FP64 brute-force oracle (no BVH, no early exit).
+
+Acceptance: every ray's FP32 visibility lies within 1e-4 of the oracle's
+value, widened only for rays that cross a Gaussian lying within binary32
+rounding of one of the cuts (t_min, 3-sigma, alpha >= 1/255); for those the
+oracle returns the band [V_lo, V_hi] spanned by both decisions.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2311_16043_amd import Gaussians, TraceParams, build_bvh, trace_rays, trace_stats, trace_visibility
+from workloads import scenes
+
+from _parity import TOL, check_vis
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(scene, dirs, params):
+    g = Gaussians.from_scene(scene)
+    bvh = build_bvh(g)
+    vr, vm = trace_visibility(bvh, g, dirs, params)
+    torch.cuda.synchronize()
+    return g, bvh, vr.cpu().numpy(), vm.cpu().numpy()
+
+
+def _oprm(params: TraceParams):
+    return oracle.params(alpha_min=1 / 255, alpha_max=0.99, sigma_cut=params.sigma_cut,
+                         tmin_scale=params.tmin_scale)
+
+
+def test_tiny_all_rays_and_means():
+    """2,000 Gaussians x 64 sphere directions: all 128,000 rays."""
+    sc = scenes.make_scene("tiny")
+    dirs = scenes.preset_dirs("tiny")
+    prm = TraceParams(dir_mode=0)
+    g, bvh, vr, vm = _run(sc, dirs, prm)
+    n, K = vr.shape
+    orc = oracle.trace_all(sc, dirs, 0, _oprm(prm))
+    check_vis(vr.reshape(-1), orc, label="tiny all rays")
+    # per-Gaussian mean: the band of the mean is the mean of the bands
+    lo = orc["V_lo"].reshape(n, K).mean(1) - TOL
+    hi = orc["V_hi"].reshape(n, K).mean(1) + TOL
+    assert np.all((vm >= lo) & (vm <= hi))
+    # and it is the FP64 mean of the FP32 rays, rounded
+    ref = (vr.astype(np.float64).sum(1) / K).astype(np.float32)
+    assert np.max(np.abs(vm - ref)) <= 1e-7
+
+
+@pytest.mark.parametrize("label,maker,K,count", [
+    ("object-20k", lambda: scenes.make_object_scene(20_000, 1), 32, 4096),
+    ("multi-4x5000", lambda: scenes.make_multi_object_scene(4, 5_000, 2), 32, 4096),
+])
+def test_small_scenes_sampled(label, maker, K, count):
+    sc = maker()
+    dirs = scenes.fibonacci_dirs(K, True)
+    prm = TraceParams()
+    g, bvh, vr, vm = _run(sc, dirs, prm)
+    ids = scenes.sample_ray_ids(sc["mean"].shape[0], K, count, seed=7)
+    orc = oracle.trace_rays(sc, dirs, 1, ids, _oprm(prm))
+    check_vis(vr.reshape(-1)[ids], orc, label=label)
+
+
+def test_object_scale_full_size_sampled():
+    """300,000 Gaussians x 256 hemisphere directions, traced in full in the
+    benchmark's launch configuration; 4,096 seeded rays checked."""
+    sc = scenes.make_scene("object")
+    dirs = scenes.preset_dirs("object")
+    prm = TraceParams()
+    g, bvh, vr, vm = _run(sc, dirs, prm)
+    n, K = vr.shape
+    ids = scenes.sample_ray_ids(n, K, 4096, seed=11)
+    orc = oracle.trace_rays(sc, dirs, 1, ids, _oprm(prm))
+    check_vis(vr.reshape(-1)[ids], orc, label="object-300k sampled")
+    assert np.all(np.isfinite(vm)) and np.all((vm >= 0) & (vm <= 1))
+
+
+def test_multi_object_full_size_sampled():
+    """1.2M Gaussians x 512 hemisphere directions; 2,048 seeded rays checked."""
+    sc = scenes.make_scene("multi")
+    dirs = scenes.preset_dirs("multi")
+    prm = TraceParams()
+    g = Gaussians.from_scene(sc)
+    bvh = build_bvh(g)
+    _, vm = trace_visibility(bvh, g, dirs, prm, want_ray=False)
+    n, K = g.n, dirs.shape[0]
+    ids = scenes.sample_ray_ids(n, K, 2048, seed=13)
+    vr = trace_rays(bvh, g, dirs, ids, prm).cpu().numpy()
+    orc = oracle.trace_rays(sc, dirs, 1, ids, _oprm(prm))
+    check_vis(vr, orc, label="multi-1.2M sampled")
+    vm = vm.cpu().numpy()
+    assert np.all(np.isfinite(vm)) and np.all((vm >= 0) & (vm <= 1))
+
+
+def test_ray_list_matches_full_trace_bitwise():
+    sc = scenes.make_object_scene(30_000, 1)
+    dirs = scenes.fibonacci_dirs(64, True)
+    prm = TraceParams()
+    g, bvh, vr, _ = _run(sc, dirs, prm)
+    ids = scenes.sample_ray_ids(30_000, 64, 20_000, seed=3)
+    got = trace_rays(bvh, g, dirs, ids, prm).cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), vr.reshape(-1)[ids].view(np.uint32))
+
+
+def test_trace_is_deterministic():
+    sc = scenes.make_object_scene(30_000, 1)
+    dirs = scenes.fibonacci_dirs(64, True)
+    g = Gaussians.from_scene(sc)
+    bvh = build_bvh(g)
+    a = trace_visibility(bvh, g, dirs)
+    b = trace_visibility(bvh, g, dirs)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_early_exit_changes_only_rays_below_tmin():
+    """Exit once T < T_min returns the running T: for every ray
+    0 <= V(T_min) - V(no exit) < T_min, and rays that never drop below T_min
+    are unchanged."""
+    sc = scenes.make_object_scene(30_000, 1)
+    dirs = scenes.fibonacci_dirs(64, True)
+    g = Gaussians.from_scene(sc)
+    bvh = build_bvh(g)
+    a, _ = trace_visibility(bvh, g, dirs, TraceParams(T_min=1e-4))
+    b, _ = trace_visibility(bvh, g, dirs, TraceParams(T_min=0.0))
+    a, b = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+    diff = a - b
+    assert np.all(diff >= -1e-12) and np.all(diff < 1e-4)
+    assert np.array_equal(a[b >= 1e-4], b[b >= 1e-4])
+    assert (b < 1e-4).sum() > 1000  # the exit is exercised
+
+
+def test_single_gaussian_and_single_direction():
+    sc = scenes.make_cube_cloud(1, 0)
+    dirs = scenes.fibonacci_dirs(8, False)
+    g, bvh, vr, vm = _run(sc, dirs, TraceParams(dir_mode=0))
+    assert np.all(vr == 1.0) and np.all(vm == 1.0)
+    sc = scenes.make_cube_cloud(500, 0)
+    dirs = scenes.fibonacci_dirs(1, False)
+    g, bvh, vr, vm = _run(sc, dirs, TraceParams(dir_mode=0))
+    orc = oracle.trace_all(sc, dirs, 0)
+    check_vis(vr.reshape(-1), orc, label="K=1")
+    assert np.array_equal(vr[:, 0], vm)
+
+
+def test_stats_are_consistent():
+    sc = scenes.make_object_scene(20_000, 1)
+    dirs = scenes.fibonacci_dirs(32, True)
+    g = Gaussians.from_scene(sc)
+    bvh = build_bvh(g)
+    st = trace_stats(bvh, g, dirs)
+    st2 = trace_stats(bvh, g, dirs)
+    assert st == st2
+    rays = 20_000 * 32
+    assert st["nodes"] >= rays and st["leaves"] >= st["hits"] > 0
+    # brute force tests n-1 Gaussians per ray; the BVH must test far fewer
+    assert st["leaves"] < 0.05 * rays * (20_000 - 1)
+    # included Gaussians agree with the oracle on a sample (up to early exit)
+    ids = scenes.sample_ray_ids(20_000, 32, 2000, seed=5)
+    orc = oracle.trace_rays(sc, dirs, 1, ids)
+    print("hits/ray gpu", st["hits"] / rays, "oracle", orc["n_incl"].mean(), flush=True)
