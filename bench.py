@@ -78,8 +78,9 @@ def main():
     rays = n * K
     vis_ray = torch.empty((n, K), dtype=torch.float32, device=dev)
     vis_mean = torch.empty((n,), dtype=torch.float32, device=dev)
-    ws = torch.empty(int(__import__("paper_2311_16043_amd")._lib.load().rv_build_workspace_bytes(n)),
-                     dtype=torch.uint8, device=dev)
+    L = __import__("paper_2311_16043_amd")._lib.load()
+    ws = torch.empty(int(L.rv_build_workspace_bytes(n)), dtype=torch.uint8, device=dev)
+    tws = torch.empty(int(L.rv_trace_workspace_bytes(n, K)), dtype=torch.uint8, device=dev)
 
     def step(ev=None):
         if ev:
@@ -87,7 +88,7 @@ def main():
         bvh = build_bvh(g, workspace=ws)
         if ev:
             ev[1].record()
-        trace_visibility(bvh, g, dirs, prm, out_ray=vis_ray, out_mean=vis_mean)
+        trace_visibility(bvh, g, dirs, prm, out_ray=vis_ray, out_mean=vis_mean, workspace=tws)
         if ev:
             ev[2].record()
         return bvh
@@ -143,7 +144,7 @@ def main():
         "trace_ms": float(np.mean(trace_ms)),
         "trace_rays_per_s": rays / trace_s,
         "roofline": {
-            "kernel": "k_trace_origins",
+            "kernel": "k_trace_chunks",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

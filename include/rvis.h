@@ -144,7 +144,7 @@ rv_status rv_bvh_view(const void *bvh, int64_t n, rv_bvh_arrays *out);
 /* Visibility (Sec. 4.1 traversal, Sec. 4.2 pre-computation)                */
 /* ------------------------------------------------------------------------ */
 
-/* Bytes of trace scratch (persistent work counter, per-ray statistics). */
+/* Bytes of trace scratch: one FP64 partial sum per (Gaussian, direction chunk). */
 size_t rv_trace_workspace_bytes(int64_t n, int32_t K);
 
 /*
@@ -152,10 +152,12 @@ size_t rv_trace_workspace_bytes(int64_t n, int32_t K);
  * ([K][3], see dir_mode), after `bvh` was built from the same g. Writes
  * vis_ray[i*K + k] = T of that ray (if vis_ray != NULL) and
  * vis_mean[i] = (1/K) sum_k T (if vis_mean != NULL); at least one of them must
- * be given. Deterministic (no atomics in the result).
+ * be given. vis_mean needs `ws` (256-byte aligned, at least
+ * rv_trace_workspace_bytes(n, K) bytes; may be NULL when vis_mean is NULL).
+ * Deterministic: the mean adds per-chunk FP64 partial sums in a fixed order.
  * Errors: RV_ERR_INVALID_ARG (null g/bvh/dirs/params, K < 1, both outputs
- * NULL, dir_mode 1 with NULL normals, out-of-range parameters),
- * RV_ERR_WORKSPACE, RV_ERR_HIP.
+ * NULL, dir_mode 1 with NULL normals, out-of-range parameters, missing or
+ * unaligned ws), RV_ERR_WORKSPACE (ws_bytes too small), RV_ERR_HIP.
  */
 rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
                               const rv_trace_params *p, float *vis_ray, float *vis_mean, void *ws,

@@ -27,7 +27,7 @@ ALPHA_MIN = 1.0 / 255.0
 ALPHA_MAX = 0.99
 SIGMA_CUT = 3.0
 TMIN_SCALE = 3.0
-KAPPA = 64.0
+KAPPA = 16.0
 
 
 def build(force: bool = True) -> str:
@@ -61,10 +61,16 @@ def lib():
             build(force=True)
         L = C.CDLL(_LIB_PATH)
         L.or_trace_rays.argtypes = [C.c_int64, _d, _d, _d, _d, _d, C.c_int32, _d, C.c_int32,
-                                    C.POINTER(_Params), C.c_int64, _i64, _d, _d, _d, _i32, _i32]
+                                    C.POINTER(_Params), C.c_int64, _i64, _d, _d, _d, _i32, _i32, _i32, _i32]
+        L.or_pair_terms.argtypes = [_d, _d, _d, C.c_int32, _d, C.c_int32, C.POINTER(_Params), C.c_int64, _i64,
+                                    C.c_int64, _d, _d, _d, C.c_double, _d, _d, _d, _i32, _i32, _i32]
+        L.or_pair_terms.restype = None
+        L.or_rays_meeting_boxes.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, C.c_int32, C.c_double,
+                                            C.c_int32, _d, _d, _u64]
+        L.or_rays_meeting_boxes.restype = None
         L.or_trace_rays.restype = None
         L.or_grad_rays.argtypes = [C.c_int64, _d, _d, _d, _d, _d, C.c_int32, _d, C.c_int32,
-                                   C.POINTER(_Params), C.c_int64, _i64, _d, _d, _d, _d]
+                                   C.POINTER(_Params), C.c_int64, _i64, _d, _d, _d, _d, C.c_int32]
         L.or_grad_rays.restype = None
         L.or_rays_meeting_box.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, C.c_int32, C.c_double,
                                           _d, _d, C.c_int64, C.c_int64, _i64]
@@ -114,10 +120,43 @@ def trace_rays(scene: dict, dirs, dir_mode: int, ray_ids, prm: _Params | None = 
     ids = np.ascontiguousarray(np.asarray(ray_ids, dtype=np.int64))
     m = ids.shape[0]
     P, lo, hi = np.empty(m), np.empty(m), np.empty(m)
-    ninc, namb = np.empty(m, np.int32), np.empty(m, np.int32)
+    ninc, namb, ncl, nnc = (np.empty(m, np.int32) for _ in range(4))
     lib().or_trace_rays(n, mean, quat, ls, op, nrm, K, dirs.reshape(-1), int(dir_mode), C.byref(prm),
-                        m, ids, P, lo, hi, ninc, namb)
-    return dict(P=P, V_lo=lo, V_hi=hi, n_incl=ninc, n_amb=namb)
+                        m, ids, P, lo, hi, ninc, namb, ncl, nnc)
+    return dict(P=P, V_lo=lo, V_hi=hi, n_incl=ninc, n_amb=namb, n_clamp=ncl, n_near_clamp=nnc)
+
+
+def pair_terms(scene: dict, dirs, dir_mode: int, ray_ids, j: int, mu=None, quat=None, log_scale=None,
+               opacity=None, prm: _Params | None = None) -> dict:
+    """Gaussian j's t*, q, alpha, inclusion and ambiguity on each listed ray;
+    j's parameters may be overridden (for perturbations)."""
+    prm = prm or params()
+    n, mean, _, ls, _, nrm = _scene64(scene)
+    dirs = _f64(dirs).reshape(-1, 3)
+    ids = np.ascontiguousarray(np.asarray(ray_ids, dtype=np.int64))
+    m = ids.shape[0]
+    mu = _f64(scene["mean"][j] if mu is None else mu)
+    qj = _f64(scene["quat"][j] if quat is None else quat)
+    lj = _f64(scene["log_scale"][j] if log_scale is None else log_scale)
+    oj = float(np.float64(scene["opacity"][j]) if opacity is None else opacity)
+    t, q, a = np.empty(m), np.empty(m), np.empty(m)
+    inc, amb, nc = np.empty(m, np.int32), np.empty(m, np.int32), np.empty(m, np.int32)
+    lib().or_pair_terms(mean, nrm, ls, dirs.shape[0], dirs.reshape(-1), int(dir_mode), C.byref(prm), m, ids,
+                        int(j), mu, qj, lj, oj, t, q, a, inc, amb, nc)
+    return dict(t=t, q=q, alpha=a, inc=inc, amb=amb, near_clamp=nc)
+
+
+def rays_meeting_boxes(scene: dict, dirs, dir_mode: int, lo, hi, tmin_scale: float = TMIN_SCALE) -> np.ndarray:
+    """uint64 mask per ray r < n*K: bit b set iff ray r's half-line meets box b (<= 64 boxes)."""
+    n, mean, _, ls, _, nrm = _scene64(scene)
+    dirs = _f64(dirs).reshape(-1, 3)
+    lo = _f64(lo).reshape(-1, 3)
+    hi = _f64(hi).reshape(-1, 3)
+    assert lo.shape == hi.shape and lo.shape[0] <= 64
+    mask = np.empty(n * dirs.shape[0], np.uint64)
+    lib().or_rays_meeting_boxes(n, mean, nrm, ls, dirs.shape[0], dirs.reshape(-1), int(dir_mode), tmin_scale,
+                                lo.shape[0], lo.reshape(-1), hi.reshape(-1), mask)
+    return mask
 
 
 def trace_all(scene: dict, dirs, dir_mode: int, prm: _Params | None = None) -> dict:
@@ -131,8 +170,11 @@ def vis_mean(P: np.ndarray, n: int, K: int) -> np.ndarray:
     return np.asarray(P, dtype=np.float64).reshape(n, K).mean(axis=1)
 
 
-def grad_rays(scene: dict, dirs, dir_mode: int, ray_ids, weights, prm: _Params | None = None) -> dict:
-    """Analytic d(sum_s w_s P_s)/d(opacity, mean, log_scale), FP64."""
+def grad_rays(scene: dict, dirs, dir_mode: int, ray_ids, weights, prm: _Params | None = None,
+              absolute: int = 0) -> dict:
+    """Analytic d(sum_s w_s P_s)/d(opacity, mean, log_scale), FP64. absolute=1
+    sums the magnitudes of its terms; absolute=2 sums each term's sensitivity
+    to binary32 rounding of the ray and of W (an error scale, without kappa)."""
     prm = prm or params()
     n, mean, quat, ls, op, nrm = _scene64(scene)
     dirs = _f64(dirs).reshape(-1, 3)
@@ -141,7 +183,7 @@ def grad_rays(scene: dict, dirs, dir_mode: int, ray_ids, weights, prm: _Params |
     assert w.shape[0] == ids.shape[0]
     go, gm, gl = np.zeros(n), np.zeros(3 * n), np.zeros(3 * n)
     lib().or_grad_rays(n, mean, quat, ls, op, nrm, dirs.shape[0], dirs.reshape(-1), int(dir_mode),
-                       C.byref(prm), ids.shape[0], ids, w, go, gm, gl)
+                       C.byref(prm), ids.shape[0], ids, w, go, gm, gl, int(absolute))
     return dict(opacity=go, mean=gm.reshape(n, 3), log_scale=gl.reshape(n, 3))
 
 

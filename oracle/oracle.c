@@ -194,7 +194,8 @@ typedef struct {
 void or_trace_rays(int64_t n, const double *mean, const double *quat, const double *log_scale,
                    const double *opacity, const double *normal, int32_t K, const double *dirs,
                    int32_t dir_mode, const or_params *prm, int64_t n_rays, const int64_t *rays,
-                   double *P, double *V_lo, double *V_hi, int32_t *n_incl, int32_t *n_amb)
+                   double *P, double *V_lo, double *V_hi, int32_t *n_incl, int32_t *n_amb, int32_t *n_clamp,
+                   int32_t *n_near_clamp)
 {
     double *W = (double *)malloc(sizeof(double) * 9 * (n > 0 ? n : 1));
     double *Wn = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
@@ -209,7 +210,7 @@ void or_trace_rays(int64_t n, const double *mean, const double *quat, const doub
         int64_t src;
         make_ray(mean, normal, log_scale, K, dirs, dir_mode, prm->tmin_scale, rays[s], o, d, &tmin, &src);
         double prod = 1.0, lo = 1.0, hi = 1.0;
-        int32_t cnt = 0, amb = 0;
+        int32_t cnt = 0, amb = 0, ncl = 0, nnc = 0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == src) continue;
             double t, q, e[3], pn, vn;
@@ -232,6 +233,9 @@ void or_trace_rays(int64_t n, const double *mean, const double *quat, const doub
             if (inc) {
                 prod *= 1.0 - ac;
                 ++cnt;
+                ncl += alpha >= prm->alpha_max;
+                /* T is continuous at the clamp but its derivative is not */
+                nnc += fabs(lna - log(prm->alpha_max)) <= err_a;
             }
             if (maybe) lo *= 1.0 - ac;
             if (sure) hi *= 1.0 - ac;
@@ -242,6 +246,8 @@ void or_trace_rays(int64_t n, const double *mean, const double *quat, const doub
         if (V_hi) V_hi[s] = hi;
         if (n_incl) n_incl[s] = cnt;
         if (n_amb) n_amb[s] = amb;
+        if (n_clamp) n_clamp[s] = ncl;
+        if (n_near_clamp) n_near_clamp[s] = nnc;
     }
     free(W);
     free(Wn);
@@ -257,11 +263,14 @@ void or_trace_rays(int64_t n, const double *mean, const double *quat, const doub
  *   dalpha/dls_{j,a} = alpha e_a^2
  *   dalpha/d(origin) = -alpha W^T e      (the origin is the source mean)
  * A clamped alpha (0.99) has zero derivative. The cuts are not differentiated.
+ * With absolute == 1 the magnitudes |term| are accumulated instead; with
+ * absolute == 2, each term's first-order sensitivity to binary32 rounding of
+ * the ray and of W (the scale of a binary32 evaluation's deviation).
  */
 void or_grad_rays(int64_t n, const double *mean, const double *quat, const double *log_scale,
                   const double *opacity, const double *normal, int32_t K, const double *dirs,
                   int32_t dir_mode, const or_params *prm, int64_t n_rays, const int64_t *rays,
-                  const double *w, double *g_opacity, double *g_mean, double *g_log_scale)
+                  const double *w, double *g_opacity, double *g_mean, double *g_log_scale, int32_t absolute)
 {
     double *W = (double *)malloc(sizeof(double) * 9 * (n > 0 ? n : 1));
     double *Wn = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
@@ -271,6 +280,8 @@ void or_grad_rays(int64_t n, const double *mean, const double *quat, const doubl
     int64_t *hit = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
     double *hit_alpha = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
     double *hit_e = (double *)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    double *hit_t = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *hit_q = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
     for (int64_t s = 0; s < n_rays; ++s) {
         double o[3], d[3], tmin;
         int64_t src;
@@ -291,6 +302,8 @@ void or_grad_rays(int64_t n, const double *mean, const double *quat, const doubl
             hit_e[3 * nh] = e[0];
             hit_e[3 * nh + 1] = e[1];
             hit_e[3 * nh + 2] = e[2];
+            hit_t[nh] = t;
+            hit_q[nh] = q;
             ++nh;
         }
         for (int64_t h = 0; h < nh; ++h) {
@@ -302,17 +315,46 @@ void or_grad_rays(int64_t n, const double *mean, const double *quat, const doubl
             const double *Wj = W + 9 * j;
             double wte[3];
             for (int c = 0; c < 3; ++c) wte[c] = Wj[c] * e[0] + Wj[3 + c] * e[1] + Wj[6 + c] * e[2];
-            g_opacity[j] += g * alpha / opacity[j];
-            for (int c = 0; c < 3; ++c) {
-                g_mean[3 * j + c] += g * alpha * wte[c];
-                g_mean[3 * src + c] -= g * alpha * wte[c];
-                g_log_scale[3 * j + c] += g * alpha * e[c] * e[c];
+            if (absolute == 2) {
+                /* sensitivity of each term to binary32 rounding of the ray (origin
+                 * difference x and direction d, ~u |x| in world units) and of W:
+                 * the whitened closest-approach vector e moves by de */
+                const double *mu = mean + 3 * j;
+                double xn = sqrt((o[0] - mu[0]) * (o[0] - mu[0]) + (o[1] - mu[1]) * (o[1] - mu[1]) +
+                                 (o[2] - mu[2]) * (o[2] - mu[2]));
+                double tj = hit_t[h];
+                double en = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+                double de = Wn[j] * (xn + fabs(tj) + 1.0) * U32;
+                double ga = fabs(g) * alpha;
+                g_opacity[j] += ga / opacity[j] * (en * de + U32 * (2.0 + hit_q[h]));
+                for (int c = 0; c < 3; ++c) {
+                    double sm = ga * (Wn[j] * de + fabs(wte[c]) * en * de);
+                    g_mean[3 * j + c] += sm;
+                    g_mean[3 * src + c] += sm;
+                    g_log_scale[3 * j + c] += ga * (2.0 * fabs(e[c]) * de + e[c] * e[c] * en * de);
+                }
+            } else if (!absolute) {
+                g_opacity[j] += g * alpha / opacity[j];
+                for (int c = 0; c < 3; ++c) {
+                    g_mean[3 * j + c] += g * alpha * wte[c];
+                    g_mean[3 * src + c] -= g * alpha * wte[c];
+                    g_log_scale[3 * j + c] += g * alpha * e[c] * e[c];
+                }
+            } else { /* sum of |term|: the scale of the summation's rounding error */
+                g_opacity[j] += fabs(g * alpha / opacity[j]);
+                for (int c = 0; c < 3; ++c) {
+                    g_mean[3 * j + c] += fabs(g * alpha * wte[c]);
+                    g_mean[3 * src + c] += fabs(g * alpha * wte[c]);
+                    g_log_scale[3 * j + c] += fabs(g * alpha * e[c] * e[c]);
+                }
             }
         }
     }
     free(hit);
     free(hit_alpha);
     free(hit_e);
+    free(hit_t);
+    free(hit_q);
     free(W);
     free(Wn);
 }
@@ -356,6 +398,87 @@ int64_t or_rays_meeting_box(int64_t n, const double *mean, const double *normal,
         }
     }
     return count;
+}
+
+/*
+ * One Gaussian's terms on a list of rays: for the Gaussian with parameters
+ * (mu, quat, log_scale, opacity) -- passed explicitly so that callers can
+ * perturb them -- and each ray s: its peak parameter t*, the squared
+ * Mahalanobis distance q at the peak, the unclamped alpha, whether it is
+ * included under the cuts, and whether that decision is ambiguous under
+ * binary32 rounding (same error model as or_trace_rays). Rays whose source
+ * index equals `self` get inc = 0 (a Gaussian never occludes its own rays).
+ */
+void or_pair_terms(const double *mean, const double *normal, const double *log_scale, int32_t K,
+                   const double *dirs, int32_t dir_mode, const or_params *prm, int64_t n_rays, const int64_t *rays,
+                   int64_t self, const double *mu_j, const double *quat_j, const double *ls_j, double o_j,
+                   double *t_out, double *q_out, double *alpha_out, int32_t *inc_out, int32_t *amb_out,
+                   int32_t *near_clamp_out)
+{
+    double W[9];
+    whitening(quat_j, ls_j, W);
+    double Wn = 0.0;
+    for (int a = 0; a < 9; ++a) Wn += W[a] * W[a];
+    Wn = sqrt(Wn);
+    const double qcut = prm->sigma_cut * prm->sigma_cut;
+    const double ln_amin = log(prm->alpha_min);
+    const double c = prm->kappa * U32;
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n_rays; ++s) {
+        double o[3], d[3], tmin;
+        int64_t src;
+        make_ray(mean, normal, log_scale, K, dirs, dir_mode, prm->tmin_scale, rays[s], o, d, &tmin, &src);
+        double t, q, e[3], pn, vn;
+        peak(W, mu_j, o, d, &t, &q, e, &pn, &vn);
+        double dist = sqrt((o[0] - mu_j[0]) * (o[0] - mu_j[0]) + (o[1] - mu_j[1]) * (o[1] - mu_j[1]) +
+                           (o[2] - mu_j[2]) * (o[2] - mu_j[2]));
+        double Pabs = Wn * dist + pn, Vabs = Wn;
+        double err_q = 2.0 * sqrt(q) * c * (Pabs + fabs(t) * Vabs) + c * (q + 1.0);
+        double err_t = c * (Pabs / vn + pn * Vabs / (vn * vn) + 2.0 * fabs(t) * Vabs / vn + tmin + fabs(t));
+        double alpha = o_j * exp(-0.5 * q);
+        double lna = log(o_j) - 0.5 * q;
+        double err_a = 0.5 * err_q + c * (2.0 + 0.5 * q + fabs(log(o_j)));
+        int inc = (src != self) && (t >= tmin) && (q <= qcut) && (alpha >= prm->alpha_min);
+        int maybe = (src != self) && (t >= tmin - err_t) && (q <= qcut + err_q) && (lna >= ln_amin - err_a);
+        int sure = (src != self) && (t >= tmin + err_t) && (q <= qcut - err_q) && (lna >= ln_amin + err_a);
+        t_out[s] = t;
+        q_out[s] = q;
+        alpha_out[s] = alpha;
+        inc_out[s] = inc;
+        amb_out[s] = maybe && !sure;
+        near_clamp_out[s] = inc && fabs(lna - log(prm->alpha_max)) <= err_a;
+    }
+}
+
+/*
+ * For every ray r < n*K and each of nb boxes, bit b of mask[r] is set iff the
+ * half-line of ray r meets box b (slab test in FP64, boxes given as lo/hi).
+ * nb <= 64.
+ */
+void or_rays_meeting_boxes(int64_t n, const double *mean, const double *normal, const double *log_scale,
+                           int32_t K, const double *dirs, int32_t dir_mode, double tmin_scale, int32_t nb,
+                           const double *lo, const double *hi, uint64_t *mask)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n * (int64_t)K; ++r) {
+        double o[3], d[3], tmin;
+        int64_t src;
+        make_ray(mean, normal, log_scale, K, dirs, dir_mode, tmin_scale, r, o, d, &tmin, &src);
+        double inv[3];
+        for (int a = 0; a < 3; ++a) inv[a] = 1.0 / d[a];
+        uint64_t bits = 0;
+        for (int b = 0; b < nb; ++b) {
+            double t0 = 0.0, t1 = INFINITY;
+            for (int a = 0; a < 3; ++a) {
+                double ta = (lo[3 * b + a] - o[a]) * inv[a], tb = (hi[3 * b + a] - o[a]) * inv[a];
+                if (ta > tb) { double tt = ta; ta = tb; tb = tt; }
+                if (ta > t0) t0 = ta;
+                if (tb < t1) t1 = tb;
+            }
+            if (t0 <= t1) bits |= 1ull << b;
+        }
+        mask[r] = bits;
+    }
 }
 
 /* ------------------------------------------------------------------------ */

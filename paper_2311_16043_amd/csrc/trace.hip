@@ -3,18 +3,26 @@
 // per-Gaussian average over the K directions (the "averaged visibility" of the
 // ablation study, Sec. 5.4).
 //
-// Work mapping: one lane per Gaussian in Morton (sorted-leaf) order, so a wave
-// holds 64 spatially adjacent origins whose rays share most of the tree. Each
-// lane walks its K rays one node per loop iteration and starts its next ray as
-// soon as the current one ends, so lanes never wait on each other's rays; the
-// per-Gaussian mean is accumulated in a register (FP64) and needs no atomics.
+// Work mapping. A wave takes 64 Gaussians adjacent in Morton (sorted-leaf)
+// order and one chunk of S consecutive directions; each lane traces its
+// Gaussian's S rays, one BVH node per loop iteration, and starts its next ray
+// as soon as the current one ends (lanes never wait on each other's rays).
+// Chunking gives ~4M lanes, so the hardware dispatcher balances the skewed
+// per-ray work across many waves instead of waiting on the slowest Gaussian.
+// Blocks are renumbered so that each XCD (round-robin dispatch) walks a
+// contiguous range of the Morton order and its L2 sees a compact part of the
+// tree. Each lane writes one FP64 partial sum; a second kernel adds a
+// Gaussian's partials in chunk order (deterministic, no atomics).
 #include "trace_core.h"
 
 namespace rv {
 namespace {
 
 constexpr int kTraceBlock = 256;
+constexpr int kWavesPerBlock = kTraceBlock / 64;
 constexpr int kRing = 16;
+constexpr int64_t kTargetLanes = 4 << 20;
+constexpr int kXcds = 8;
 
 struct Origin {
     f3 o, nrm, b1, b2;
@@ -35,17 +43,62 @@ __device__ __forceinline__ Origin load_origin(const float4 *__restrict__ rec, co
     return g;
 }
 
+// Chunking of the n*K rays: n_chunks chunks of S directions per Gaussian.
+struct ChunkMap {
+    int64_t n;
+    int K, S, n_chunks;
+    int64_t n_items;   // waves of work: ceil(n / 64) * n_chunks
+    int64_t n_blocks;
+};
+
+inline ChunkMap make_chunks(int64_t n, int K) {
+    ChunkMap cm;
+    cm.n = n;
+    cm.K = K;
+    int64_t want = (kTargetLanes + n - 1) / n;
+    if (want < 1) want = 1;
+    if (want > K) want = K;
+    cm.S = (int)((K + want - 1) / want);
+    cm.n_chunks = (K + cm.S - 1) / cm.S;
+    cm.n_items = ((n + 63) / 64) * (int64_t)cm.n_chunks;
+    cm.n_blocks = (cm.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
+    return cm;
+}
+
+// Renumber blocks so that the blocks dispatched to XCD x (b % 8 == x) form a
+// contiguous range of logical blocks. A bijection on [0, nb).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t q = nb / kXcds, r = nb % kXcds;
+    const int64_t x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
+// This lane's Gaussian (sorted position m), chunk and direction range.
+__device__ __forceinline__ bool lane_work(const ChunkMap &cm, int64_t &m, int &chunk, int &k0, int &k1) {
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t w = b * kWavesPerBlock + threadIdx.x / 64;
+    if (w >= cm.n_items) return false;
+    const int64_t grp = w / cm.n_chunks;
+    chunk = (int)(w - grp * cm.n_chunks);
+    m = grp * 64 + (threadIdx.x & 63);
+    if (m >= cm.n) return false;
+    k0 = chunk * cm.S;
+    k1 = min(cm.K, k0 + cm.S);
+    return true;
+}
+
 template <bool kCount>
-__global__ __launch_bounds__(kTraceBlock) void k_trace_origins(const float4 *__restrict__ nodes,
-                                                               const float4 *__restrict__ rec,
-                                                               const float4 *__restrict__ origins, int64_t n,
-                                                               const float *__restrict__ dirs, int K, Cuts c,
-                                                               float *__restrict__ vis_ray,
-                                                               float *__restrict__ vis_mean,
-                                                               unsigned long long *__restrict__ totals) {
+__global__ __launch_bounds__(kTraceBlock) void k_trace_chunks(const float4 *__restrict__ nodes,
+                                                              const float4 *__restrict__ rec,
+                                                              const float4 *__restrict__ origins,
+                                                              const float *__restrict__ dirs, ChunkMap cm, Cuts c,
+                                                              float *__restrict__ vis_ray,
+                                                              double *__restrict__ partial,
+                                                              unsigned long long *__restrict__ totals) {
     __shared__ int32_t lds[kRing * kTraceBlock];
-    const int64_t m = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
-    if (m >= n) return;
+    int64_t m;
+    int chunk, k0, k1;
+    if (!lane_work(cm, m, chunk, k0, k1)) return;
     const Origin g = load_origin(rec, origins, m, c);
     RayState<kRing> rs;
     rs.st.lds = lds + threadIdx.x;
@@ -53,23 +106,33 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_origins(const float4 *__r
     NoHit none;
     int64_t cn = 0, cl = 0, ch = 0;
     double sum = 0.0;
-    int k = 0;
-    rs.start(g.o, ray_direction(dirs, 0, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, n);
+    int k = k0;
+    rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, cm.n);
     while (true) {
         const bool done = rs.node < 0 || rs.template step<NoHit, kCount>(nodes, rec, c, none, &cn, &cl, &ch);
         if (done) {
-            if (vis_ray) vis_ray[(int64_t)g.src * K + k] = rs.T;
+            if (vis_ray) vis_ray[(int64_t)g.src * cm.K + k] = rs.T;
             sum += (double)rs.T;
-            if (++k == K) break;
-            rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, n);
+            if (++k == k1) break;
+            rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, cm.n);
         }
     }
-    if (vis_mean) vis_mean[g.src] = (float)(sum / (double)K);
+    if (partial) partial[(int64_t)chunk * cm.n + g.src] = sum;
     if (kCount) {
         atomicAdd(totals + 0, (unsigned long long)cn);
         atomicAdd(totals + 1, (unsigned long long)cl);
         atomicAdd(totals + 2, (unsigned long long)ch);
     }
+}
+
+// vis_mean[i] = (sum over chunks, in chunk order, of the FP64 partials) / K.
+__global__ __launch_bounds__(256) void k_mean_from_partials(const double *__restrict__ partial, int64_t n,
+                                                            int n_chunks, int K, float *__restrict__ vis_mean) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < n_chunks; ++c) s += partial[(int64_t)c * n + i];
+    vis_mean[i] = (float)(s / (double)K);
 }
 
 // One lane per listed ray; origin data recomputed from the input arrays with
@@ -122,7 +185,7 @@ struct GradScatter {
 
     __device__ __forceinline__ void operator()(const LeafHit &h, float) {
         if (h.clamped) return;
-        const float ga = g_over / (1.0f - h.alpha);   // dL/dalpha
+        const float ga = g_over / h.one_minus;   // dL/dalpha
         const float a = ga * h.alpha;
         const f3 wte = h.e.x * h.w0 + h.e.y * h.w1 + h.e.z * h.w2;   // W^T e
         const int64_t j = h.src;
@@ -138,12 +201,14 @@ struct GradScatter {
 };
 
 __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
-    const float4 *__restrict__ nodes, const float4 *__restrict__ rec, const float4 *__restrict__ origins, int64_t n,
-    const float *__restrict__ dirs, int K, Cuts c, const float *__restrict__ grad_ray,
+    const float4 *__restrict__ nodes, const float4 *__restrict__ rec, const float4 *__restrict__ origins,
+    const float *__restrict__ dirs, ChunkMap cm, Cuts c, const float *__restrict__ grad_ray,
     const float *__restrict__ grad_mean_in, const float *__restrict__ vis_fwd, float *go, float *gm, float *gl) {
     __shared__ int32_t lds[kRing * kTraceBlock];
-    const int64_t m = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
-    if (m >= n) return;
+    int64_t m;
+    int chunk, k0, k1;
+    if (!lane_work(cm, m, chunk, k0, k1)) return;
+    const int K = cm.K;
     const Origin g = load_origin(rec, origins, m, c);
     RayState<kRing> rs;
     rs.st.lds = lds + threadIdx.x;
@@ -155,18 +220,18 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     gs.gl = gl;
     gs.origin = mk(0.f, 0.f, 0.f);
     const float gmean = grad_mean_in ? grad_mean_in[g.src] / (float)K : 0.0f;
-    int k = 0;
+    int k = k0;
     int phase = 0;
     float gk = 0.0f;
-    // find the first ray with a nonzero upstream gradient
+    // next ray of this lane's chunk with a nonzero upstream gradient
     auto begin_ray = [&](int kk) -> bool {
-        for (; kk < K; ++kk) {
+        for (; kk < k1; ++kk) {
             gk = gmean + (grad_ray ? grad_ray[(int64_t)g.src * K + kk] : 0.0f);
             if (gk != 0.0f) break;
         }
         k = kk;
-        if (k >= K) return false;
-        rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, n);
+        if (k >= k1) return false;
+        rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, cm.n);
         if (vis_fwd) {
             phase = 1;
             gs.g_over = -gk * vis_fwd[(int64_t)g.src * K + k];
@@ -175,14 +240,15 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
         }
         return true;
     };
-    bool live = begin_ray(0);
+    bool live = begin_ray(k0);
     while (live) {
         bool done;
         if (phase == 0) {
+            // first pass: the ray's final T (same traversal, same early exit)
             done = rs.node < 0 || rs.step(nodes, rec, c, none);
             if (done) {
                 gs.g_over = -gk * rs.T;
-                rs.start(rs.o, rs.d, rs.tmin, rs.self, n);
+                rs.start(rs.o, rs.d, rs.tmin, rs.self, cm.n);
                 phase = 1;
             }
         } else {
@@ -227,9 +293,9 @@ rv_status validate_trace(const char *fn, const void *bvh, const rv_gaussians *g,
 using namespace rv;
 
 extern "C" size_t rv_trace_workspace_bytes(int64_t n, int32_t K) {
-    (void)n;
-    (void)K;
-    return kAlign;
+    if (n < 1 || K < 1) return kAlign;
+    const ChunkMap cm = make_chunks(n, K);
+    return align_up((size_t)cm.n_chunks * (size_t)n * sizeof(double)) + kAlign;
 }
 
 extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
@@ -239,14 +305,24 @@ extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g,
     rv_status st = validate_trace("rv_trace_visibility", bvh, g, dirs, K, p);
     if (st != RV_OK) return st;
     RV_REQUIRE(vis_ray || vis_mean, RV_ERR_INVALID_ARG, "rv_trace_visibility: both outputs are NULL");
-    (void)ws;
-    (void)ws_bytes;
+    const ChunkMap cm = make_chunks(g->n, K);
+    double *partial = nullptr;
+    if (vis_mean) {
+        RV_REQUIRE(ws && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG,
+                   "rv_trace_visibility: vis_mean needs a 256-byte aligned workspace");
+        RV_REQUIRE(ws_bytes >= rv_trace_workspace_bytes(g->n, K), RV_ERR_WORKSPACE,
+                   "rv_trace_visibility: ws_bytes %zu < %zu", ws_bytes, rv_trace_workspace_bytes(g->n, K));
+        partial = static_cast<double *>(ws);
+    }
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
-    hipLaunchKernelGGL(k_trace_origins<false>, dim3(grid_for(g->n, kTraceBlock)), dim3(kTraceBlock), 0,
-                       (hipStream_t)stream, at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec),
-                       at<float4>(bvh, L.origins), g->n, dirs, K, c, vis_ray, vis_mean,
-                       (unsigned long long *)nullptr);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_trace_chunks<false>, dim3((unsigned)cm.n_blocks), dim3(kTraceBlock), 0, s,
+                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, cm, c,
+                       vis_ray, partial, (unsigned long long *)nullptr);
+    if (vis_mean)
+        hipLaunchKernelGGL(k_mean_from_partials, dim3(grid_for(g->n, 256)), dim3(256), 0, s, partial, g->n,
+                           cm.n_chunks, K, vis_mean);
     return check_launch("rv_trace_visibility");
 }
 
@@ -259,14 +335,15 @@ extern "C" rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, cons
     RV_REQUIRE(totals, RV_ERR_INVALID_ARG, "rv_trace_stats: null totals");
     (void)ws;
     (void)ws_bytes;
+    const ChunkMap cm = make_chunks(g->n, K);
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(totals), (int64_t)6,
                        0u);
-    hipLaunchKernelGGL(k_trace_origins<true>, dim3(grid_for(g->n, kTraceBlock)), dim3(kTraceBlock), 0, s,
-                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), g->n,
-                       dirs, K, c, (float *)nullptr, (float *)nullptr, (unsigned long long *)totals);
+    hipLaunchKernelGGL(k_trace_chunks<true>, dim3((unsigned)cm.n_blocks), dim3(kTraceBlock), 0, s,
+                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, cm, c,
+                       (float *)nullptr, (double *)nullptr, (unsigned long long *)totals);
     return check_launch("rv_trace_stats");
 }
 
@@ -299,11 +376,11 @@ extern "C" rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaus
                "rv_trace_visibility_backward: both upstream gradients are NULL");
     RV_REQUIRE(grad_opacity && grad_mean && grad_log_scale, RV_ERR_INVALID_ARG,
                "rv_trace_visibility_backward: null gradient output");
+    const ChunkMap cm = make_chunks(g->n, K);
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
-    hipLaunchKernelGGL(k_trace_backward, dim3(grid_for(g->n, kTraceBlock)), dim3(kTraceBlock), 0,
-                       (hipStream_t)stream, at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec),
-                       at<float4>(bvh, L.origins), g->n, dirs, K, c, grad_vis_ray, grad_vis_mean, vis_ray_fwd,
-                       grad_opacity, grad_mean, grad_log_scale);
+    hipLaunchKernelGGL(k_trace_backward, dim3((unsigned)cm.n_blocks), dim3(kTraceBlock), 0, (hipStream_t)stream,
+                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, cm, c,
+                       grad_vis_ray, grad_vis_mean, vis_ray_fwd, grad_opacity, grad_mean, grad_log_scale);
     return check_launch("rv_trace_visibility_backward");
 }

@@ -76,6 +76,7 @@ __device__ __forceinline__ bool slab_hit(float lx, float ly, float lz, float hx,
 // What a leaf test hands to a hit callback.
 struct LeafHit {
     float alpha;     // unclamped alpha = o exp(-q/2)
+    float one_minus; // the factor applied to T: 1 - min(alpha, alpha_max)
     bool clamped;    // alpha >= alpha_max (contribution used min(alpha, alpha_max))
     float opacity;
     int32_t src;     // original index of the Gaussian
@@ -111,20 +112,28 @@ __device__ __forceinline__ float leaf_factor(const float4 *__restrict__ rec, int
     const f3 cp = cross(p, v);
     const float q = dot(cp, cp) * inv_vv;
     if (!(q <= c.q_cut)) return 1.0f;
-    const float alpha = r0.w * __expf(-0.5f * q);
+    // alpha = o e^{-q/2} = o + o m with m = e^{-q/2} - 1. For small q, m comes
+    // from expm1 so that 1 - alpha = (1 - o) - o m keeps full relative
+    // precision when alpha approaches 1 (the adjoint divides by it).
+    const float ex = -0.5f * q;
+    const float em1 = q < 0.5f ? expm1f(ex) : __expf(ex) - 1.0f;
+    const float op = r0.w;
+    const float alpha = op + op * em1;
     if (!(alpha >= c.alpha_min)) return 1.0f;
-    const float ac = fminf(alpha, c.alpha_max);
+    const bool clamped = alpha >= c.alpha_max;
+    const float one_minus = clamped ? 1.0f - c.alpha_max : (1.0f - op) - op * em1;
     LeafHit h;
     h.alpha = alpha;
-    h.clamped = alpha >= c.alpha_max;
-    h.opacity = r0.w;
+    h.one_minus = one_minus;
+    h.clamped = clamped;
+    h.opacity = op;
     h.src = src;
     h.e = p + t * v;
     h.w0 = w0;
     h.w1 = w1;
     h.w2 = w2;
     on_hit(h, T_before);
-    return 1.0f - ac;
+    return one_minus;
 }
 
 // LDS ring holding the top kRing stack entries of each lane (slot-major, so a

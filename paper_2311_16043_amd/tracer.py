@@ -145,7 +145,7 @@ def _dirs(dirs, device) -> torch.Tensor:
 
 def trace_visibility(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = None,
                      want_ray: bool = True, want_mean: bool = True, out_ray: torch.Tensor | None = None,
-                     out_mean: torch.Tensor | None = None):
+                     out_mean: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
     """(vis_ray [n, K] or None, vis_mean [n] or None) for every ray (i, k)."""
     params = params or TraceParams()
     dev = g.mean.device
@@ -153,10 +153,13 @@ def trace_visibility(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = 
     K = int(d.shape[0])
     vr = (out_ray if out_ray is not None else torch.empty((g.n, K), dtype=_F32, device=dev)) if want_ray else None
     vm = (out_mean if out_mean is not None else torch.empty((g.n,), dtype=_F32, device=dev)) if want_mean else None
+    ws_bytes = _lib.load().rv_trace_workspace_bytes(g.n, K)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc_bytes(ws_bytes, dev)
     gc, pc = g.c(), params.c()
     _lib.call("rv_trace_visibility", bvh.ptr, C.byref(gc), d.data_ptr(), K, C.byref(pc),
-              None if vr is None else vr.data_ptr(), None if vm is None else vm.data_ptr(), None, 0,
-              _stream_ptr(dev))
+              None if vr is None else vr.data_ptr(), None if vm is None else vm.data_ptr(), workspace.data_ptr(),
+              workspace.numel(), _stream_ptr(dev))
     return vr, vm
 
 

@@ -1,0 +1,274 @@
+"""Adjoint of the tracer: d/d(opacity, mean, log_scale) of sum_r g_r T_r.
+
+1. Small scene: the GPU adjoint against the oracle's analytic FP64 gradient
+   (itself pinned to finite differences in test_oracle_pins.py), every ray.
+2. Differentiation workload at full size (200,000 object-scale Gaussians x 128
+   hemisphere directions): 64 seeded parameters against FP64 central finite
+   differences of the oracle (h = 1e-4, plus a Richardson step), relative
+   error <= 1e-3 with the denominator max(|g_fd|, 1e-3 RMS over the 64).
+   T_min = 0 in both; a parameter is redrawn if any affected ray changes its
+   included set, its clamp state or is ambiguous under binary32 rounding
+   between theta - h and theta + h (the cuts make T piecewise smooth).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2311_16043_amd import Gaussians, TraceParams, build_bvh, trace_visibility, trace_visibility_backward
+from paper_2311_16043_amd.autograd import visibility
+from workloads import scenes
+
+pytestmark = pytest.mark.gpu
+
+NO_EXIT = TraceParams(T_min=0.0)
+KAPPA_G = 8.0
+
+
+def _gpu_grads(sc, dirs, prm, grad_ray=None, grad_mean=None, use_fwd=False):
+    g = Gaussians.from_scene(sc)
+    bvh = build_bvh(g)
+    vr = None
+    if use_fwd:
+        vr, _ = trace_visibility(bvh, g, dirs, prm)
+    go, gm, gl = trace_visibility_backward(
+        bvh, g, dirs, prm,
+        grad_vis_ray=None if grad_ray is None else torch.from_numpy(grad_ray.astype(np.float32)),
+        grad_vis_mean=None if grad_mean is None else torch.from_numpy(grad_mean.astype(np.float32)),
+        vis_ray_fwd=vr)
+    torch.cuda.synchronize()
+    return go.cpu().numpy(), gm.cpu().numpy(), gl.cpu().numpy()
+
+
+def _rel(a, b, floor):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+@pytest.mark.parametrize("use_fwd", [False, True])
+def test_adjoint_matches_oracle_analytic_small(use_fwd):
+    sc = scenes.make_object_scene(3000, 3)
+    K = 16
+    dirs = scenes.fibonacci_dirs(K, True)
+    n = 3000
+    rays = np.arange(n * K, dtype=np.int64)
+    orc = oracle.trace_rays(sc, dirs, 1, rays)
+    rng = np.random.default_rng(42)
+    w = rng.uniform(-1.0, 1.0, n * K)
+    # rays whose included set or clamp state binary32 may decide differently carry no gradient
+    w[(orc["n_amb"] > 0) | (orc["n_near_clamp"] > 0)] = 0.0
+    ref = oracle.grad_rays(sc, dirs, 1, rays, w)
+    sens = oracle.grad_rays(sc, dirs, 1, rays, w, absolute=2)
+    go, gm, gl = _gpu_grads(sc, dirs, NO_EXIT, grad_ray=w.reshape(n, K), use_fwd=use_fwd)
+    for name, got, exp in (("opacity", go, ref["opacity"]), ("mean", gm, ref["mean"]),
+                           ("log_scale", gl, ref["log_scale"])):
+        rms = float(np.sqrt(np.mean(exp ** 2)))
+        diff = np.abs(got.astype(np.float64) - exp)
+        # 1e-3 relative, widened by kappa = 8 times each element's first-order
+        # sensitivity to binary32 rounding of the rays and of W (far-field
+        # near-misses of thin Gaussians: |p| ~ 1e3 whitened units)
+        tol = 1e-3 * np.maximum(np.abs(exp), 1e-3 * rms) + KAPPA_G * sens[name]
+        err = _rel(got.astype(np.float64), exp, 1e-3 * rms)
+        print(f"[adjoint small {name}] rms {rms:.3e} rel err max {err.max():.2e} p50 {np.median(err):.2e} "
+              f"p99 {np.quantile(err, 0.99):.2e}; max diff/tol {np.max(diff / tol):.3f}", flush=True)
+        assert np.all(diff <= tol), name
+        assert np.median(err) <= 1e-4
+        assert rms > 0
+
+
+def test_adjoint_mean_gradient_path_and_autograd():
+    """grad_vis_mean routes to every ray as g/K; autograd wires the same kernel."""
+    sc = scenes.make_object_scene(2000, 3)
+    K = 8
+    dirs = scenes.fibonacci_dirs(K, True)
+    n = 2000
+    y = np.random.default_rng(3).uniform(0, 1, n)
+    rays = np.arange(n * K, dtype=np.int64)
+    orc = oracle.trace_rays(sc, dirs, 1, rays)
+    gm_up = np.random.default_rng(4).uniform(-1, 1, n)
+    amb_src = np.unique(rays[(orc["n_amb"] > 0) | (orc["n_near_clamp"] > 0)] // K)
+    gm_up[amb_src] = 0.0
+    ref = oracle.grad_rays(sc, dirs, 1, rays, np.repeat(gm_up / K, K))
+    go, gm, gl = _gpu_grads(sc, dirs, NO_EXIT, grad_mean=gm_up)
+    sens = oracle.grad_rays(sc, dirs, 1, rays, np.repeat(gm_up / K, K), absolute=2)
+    rms = np.sqrt(np.mean(ref["mean"] ** 2))
+    tol = 1e-3 * np.maximum(np.abs(ref["mean"]), 1e-3 * rms) + KAPPA_G * sens["mean"]
+    assert np.all(np.abs(gm.astype(np.float64) - ref["mean"]) <= tol)
+    # autograd: loss = mean((V - y)^2) restricted to unambiguous Gaussians
+    dev = torch.device("cuda")
+    t = {k: torch.from_numpy(v).to(dev) for k, v in sc.items()}
+    op = t["opacity"].clone().requires_grad_(True)
+    mu = t["mean"].clone().requires_grad_(True)
+    ls = t["log_scale"].clone().requires_grad_(True)
+    vm, vr = visibility(op, mu, ls, t["quat"], t["normal"], torch.from_numpy(dirs).to(dev), NO_EXIT)
+    keep = torch.ones(n, device=dev)
+    keep[torch.from_numpy(amb_src).to(dev)] = 0
+    loss = (((vm - torch.from_numpy(y.astype(np.float32)).to(dev)) ** 2) * keep).mean()
+    loss.backward()
+    up = (2.0 / n) * (orc["P"].reshape(n, K).mean(1) - y) * keep.cpu().numpy()
+    ref = oracle.grad_rays(sc, dirs, 1, rays, np.repeat(up / K, K))
+    sens = oracle.grad_rays(sc, dirs, 1, rays, np.repeat(up / K, K), absolute=2)
+    for name, got in (("opacity", op.grad), ("mean", mu.grad), ("log_scale", ls.grad)):
+        exp = np.asarray(ref[name])
+        rms = np.sqrt(np.mean(exp ** 2))
+        tol = 2e-3 * np.maximum(np.abs(exp), 1e-3 * rms) + KAPPA_G * sens[name]
+        assert np.all(np.abs(got.cpu().numpy().astype(np.float64) - exp) <= tol), name
+
+
+def _fd_sample(sc, dirs, K, n_params, seed, h=1e-4):
+    """Seeded (kind, j, comp) parameters with FP64 central differences of
+    F = sum_r w_r P_r, restricted to the rays each parameter can change.
+
+    w_r = w_i / K with w_i ~ U[-1, 1] per Gaussian (the form of dL/dVbar of a
+    squared-error loss), except that rays on which binary32 and FP64 may take
+    different decisions (an ambiguous pair, a pair near the clamp, or a cut or
+    clamp state that changes within +-h of a sampled parameter) get w_r = 0.
+    The same per-ray weights drive the GPU adjoint. Returns the parameters and
+    the weights [n, K].
+    """
+    n = sc["mean"].shape[0]
+    rng = np.random.default_rng(seed)
+    w_g = rng.uniform(-1.0, 1.0, n)
+    w_ray = np.repeat(w_g / K, K)
+    bad = np.zeros(n * K, bool)
+    kinds = ("opacity", "mean", "log_scale")
+    cands = []
+    while len(cands) < 2 * n_params:
+        j = int(rng.integers(n))
+        kind = kinds[int(rng.integers(3))]
+        comp = 0 if kind == "opacity" else int(rng.integers(3))
+        cands.append((kind, j, comp))
+    lo_all, hi_all = oracle.leaf_boxes(sc)
+    prm = oracle.params()
+    u = 2.0 ** -24
+    recs = []
+    for c0 in range(0, len(cands), 64):
+        if len(recs) >= n_params:
+            break
+        chunk = cands[c0:c0 + 64]
+        js = np.array([c[1] for c in chunk])
+        pad = 0.01
+        mask = oracle.rays_meeting_boxes(sc, dirs, 1, lo_all[js] - pad, hi_all[js] + pad)
+        for b, (kind, j, comp) in enumerate(chunk):
+            if len(recs) >= n_params:
+                break
+            own = np.arange(j * K, (j + 1) * K, dtype=np.int64)
+            ids = np.nonzero((mask >> np.uint64(b)) & np.uint64(1))[0].astype(np.int64)
+            ids = np.setdiff1d(ids, own)
+            base = np.asarray(sc[kind][j], np.float64).copy()
+            arg = {"opacity": "opacity", "mean": "mu", "log_scale": "log_scale"}[kind]
+
+            def terms(delta):
+                v = base + delta if kind == "opacity" else base.copy()
+                if kind != "opacity":
+                    v[comp] += delta
+                return oracle.pair_terms(sc, dirs, 1, ids, j, **{arg: float(v) if kind == "opacity" else v})
+
+            T = {d: terms(d) for d in (0.0, h, -h, h / 2, -h / 2)}
+            tz = T[0.0]
+            clamp = lambda t: (t["alpha"] >= 0.99) & (t["inc"] > 0)
+            flag = tz["near_clamp"].astype(bool)
+            for d in T:
+                flag |= T[d]["amb"].astype(bool) | (T[d]["inc"] != tz["inc"]) | (clamp(T[d]) != clamp(tz))
+            live = (tz["inc"] > 0) & ~flag
+            bad[ids[flag]] = True
+            ids_l = ids[live]
+            rec = dict(kind=kind, j=j, comp=comp, ids=ids_l, rays=int(ids_l.size))
+            if ids_l.size:
+                o0 = oracle.trace_rays(sc, dirs, 1, ids_l, prm)
+                bad[ids_l[(o0["n_amb"] > 0) | (o0["n_near_clamp"] > 0)]] = True
+
+                def fac(t):
+                    a = np.minimum(t["alpha"][live], 0.99)
+                    return np.where(t["inc"][live] > 0, 1.0 - a, 1.0)
+
+                f0 = fac(tz)
+                # P changes only through Gaussian j's factor (the Eq. (15) product)
+                rec["c1"] = o0["P"] * (fac(T[h]) - fac(T[-h])) / f0 / (2 * h)
+                rec["c2"] = o0["P"] * (fac(T[h / 2]) - fac(T[-h / 2])) / f0 / h
+                # binary32 sensitivity of j's own terms (oracle.grad_rays absolute=2, with |W^T e| <= |W||e|)
+                Wn = np.linalg.norm(oracle.whitening(np.asarray(sc["quat"][j], np.float64),
+                                                     np.asarray(sc["log_scale"][j], np.float64)))
+                xn = np.linalg.norm(np.asarray(sc["mean"][ids_l // K], np.float64) -
+                                    np.asarray(sc["mean"][j], np.float64), axis=1)
+                en = np.sqrt(tz["q"][live])
+                de = Wn * (xn + np.abs(tz["t"][live]) + 1.0) * u
+                ga = o0["P"] / f0 * tz["alpha"][live]
+                if kind == "opacity":
+                    rec["s"] = ga / float(sc["opacity"][j]) * (en * de + u * (2.0 + tz["q"][live]))
+                elif kind == "mean":
+                    rec["s"] = ga * (Wn * de + Wn * en * en * de)
+                else:
+                    rec["s"] = ga * (2.0 * en * de + en ** 3 * de)
+            rec["own_c1"] = rec["own_c2"] = None
+            rec["own_sens"] = 0.0
+            if kind in ("mean", "log_scale"):
+                # the mean moves the origin of j's own rays, the log-scale their t_min
+                res = {}
+                for dlt in (0.0, h, -h, h / 2, -h / 2):
+                    s2 = {k: v.copy() for k, v in sc.items()}
+                    s2[kind] = s2[kind].astype(np.float64)
+                    s2[kind][j, comp] += dlt
+                    res[dlt] = oracle.trace_rays(s2, dirs, 1, own, prm)
+                r0 = res[0.0]
+                oflag = np.zeros(K, bool)
+                for dlt in res:
+                    oflag |= (res[dlt]["n_incl"] != r0["n_incl"]) | (res[dlt]["n_amb"] > 0) | \
+                             (res[dlt]["n_near_clamp"] > 0) | (res[dlt]["n_clamp"] != r0["n_clamp"])
+                bad[own[oflag]] = True
+                rec["own_c1"] = (res[h]["P"] - res[-h]["P"]) / (2 * h)
+                rec["own_c2"] = (res[h / 2]["P"] - res[-h / 2]["P"]) / h
+                if kind == "mean":
+                    so = oracle.grad_rays(sc, dirs, 1, own, np.abs(w_ray[own]), prm, absolute=2)
+                    rec["own_sens"] = float(so["mean"][j, comp])
+            recs.append(rec)
+    w_ray[bad] = 0.0
+    out = []
+    for r in recs:
+        fd = fd2 = sens = 0.0
+        if r["rays"]:
+            wv = w_ray[r["ids"]]
+            fd, fd2 = float(np.dot(wv, r["c1"])), float(np.dot(wv, r["c2"]))
+            sens = float(np.dot(np.abs(wv), r["s"]))
+        if r["own_c1"] is not None:
+            wo = w_ray[r["j"] * K:(r["j"] + 1) * K]
+            fd += float(np.dot(wo, r["own_c1"]))
+            fd2 += float(np.dot(wo, r["own_c2"]))
+        sens += r["own_sens"]
+        out.append(dict(kind=r["kind"], j=r["j"], comp=r["comp"], fd=fd, rich=(4.0 * fd2 - fd) / 3.0, sens=sens,
+                        rays=r["rays"]))
+    print(f"[adjoint fd] {len(out)} parameters, {int(bad.sum())} of {bad.size} rays masked", flush=True)
+    return out, w_ray.reshape(n, K)
+
+
+def test_adjoint_fd_differentiation_workload_full_size():
+    """200,000 Gaussians x 128 directions, 64 sampled parameters."""
+    sc = scenes.make_scene("diff")
+    K = scenes.PRESETS["diff"]["K"]
+    dirs = scenes.preset_dirs("diff")
+    n = sc["mean"].shape[0]
+    params, w_ray = _fd_sample(sc, dirs, K, 64, seed=2024)
+    assert len(params) == 64
+    go, gm, gl = _gpu_grads(sc, dirs, NO_EXIT, grad_ray=w_ray)
+    got = np.array([go[p["j"]] if p["kind"] == "opacity" else (gm if p["kind"] == "mean" else gl)[p["j"], p["comp"]]
+                    for p in params], np.float64)
+    rich = np.array([p["rich"] for p in params])
+    fd = np.array([p["fd"] for p in params])
+    sens = np.array([p["sens"] for p in params])
+    floor = 1e-3 * np.sqrt(np.mean(rich ** 2))
+    err_rich = _rel(got, rich, floor)
+    err_fd = _rel(got, fd, floor)
+    # relative error <= 1e-3 (denominator max(|g_fd|, 1e-3 RMS)); a parameter
+    # whose binary32 ray-rounding sensitivity exceeds that is held to kappa x it
+    ok_rel = err_rich <= 1e-3
+    ok_sens = np.abs(got - rich) <= KAPPA_G * sens
+    print(f"[adjoint fd full] params {len(params)}, nonzero {(np.abs(rich) > floor).sum()}, rays/param "
+          f"{np.mean([p['rays'] for p in params]):.0f}; rel err vs Richardson max {err_rich.max():.2e} "
+          f"median {np.median(err_rich):.2e}; vs plain h=1e-4 max {err_fd.max():.2e} median {np.median(err_fd):.2e}; "
+          f"within 1e-3: {ok_rel.sum()}, within the binary32 bound only: {(~ok_rel & ok_sens).sum()}", flush=True)
+    for p, e, ok in zip(params, err_rich, ok_rel):
+        if not ok:
+            print(f"   {p['kind']}[{p['j']},{p['comp']}] rel {e:.2e} sens/|g| {p['sens'] / max(abs(p['rich']), 1e-30):.2e}")
+    assert np.all(ok_rel | ok_sens)
+    assert ok_rel.mean() >= 0.9
