@@ -24,6 +24,30 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+KERNEL_SOURCES = ["paper_2311_16043_amd/csrc/trace.hip", "paper_2311_16043_amd/csrc/trace_core.h",
+                  "paper_2311_16043_amd/csrc/build.hip", "paper_2311_16043_amd/csrc/rv_internal.h"]
+COUNTERS_FILE = "profiles/trace_object_scale_counters.md"
+
+
+def recorded_traffic():
+    """HBM bytes per launch from the committed counter profile, if it was taken
+    on the kernel sources as they are now (else None)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        text = open(os.path.join(ROOT, COUNTERS_FILE)).read()
+    except OSError:
+        return None
+    kv = dict(line.strip().split(": ", 1) for line in text.splitlines() if ": " in line and
+              line.strip().split(": ", 1)[0] in ("kernel_sources_sha256_16", "traffic_bytes_per_launch"))
+    if kv.get("kernel_sources_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -32,7 +56,26 @@ def parse():
     ap.add_argument("--workload", default="object", choices=["object", "multi", "tiny"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the streaming-copy probe (known-size reference for counters)")
     return ap.parse_args()
+
+
+def copy_probe(torch, nbytes=1 << 31, iters=5):
+    """Achievable HBM bandwidth of the library's streaming copy: read + write bytes / time."""
+    from paper_2311_16043_amd import stream_copy
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    stream_copy(src, dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        stream_copy(src, dst)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1000.0 / iters
+    return dict(bytes_per_copy=nbytes, gbs=2 * nbytes / dt / 1e9, ms=dt * 1000.0)
 
 
 def cpu_baseline(scene, dirs, dir_mode, target_s):
@@ -40,11 +83,14 @@ def cpu_baseline(scene, dirs, dir_mode, target_s):
     import oracle
     from workloads import scenes
     n, K = scene["mean"].shape[0], dirs.shape[0]
-    pilot = scenes.sample_ray_ids(n, K, 64, seed=99)
+    t = time.perf_counter()
+    oracle.trace_rays(scene, dirs, dir_mode, scenes.sample_ray_ids(n, K, 1, seed=98))
+    setup = time.perf_counter() - t
+    pilot = scenes.sample_ray_ids(n, K, 512, seed=99)
     t = time.perf_counter()
     oracle.trace_rays(scene, dirs, dir_mode, pilot)
-    per_ray = (time.perf_counter() - t) / pilot.size
-    count = int(max(64, min(1 << 16, target_s / max(per_ray, 1e-9))))
+    per_ray = max(time.perf_counter() - t - setup, 1e-3) / pilot.size
+    count = int(max(64, min(1 << 18, target_s / max(per_ray, 1e-9))))
     ids = scenes.sample_ray_ids(n, K, count, seed=100)
     t = time.perf_counter()
     oracle.trace_rays(scene, dirs, dir_mode, ids)
@@ -67,6 +113,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        print(json.dumps({"copy_probe": copy_probe(torch)}), flush=True)
+        return
     name = args.workload
     sc = scenes.make_scene(name)
     dirs_np = scenes.preset_dirs(name)
@@ -150,7 +199,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": recorded_traffic() if name == "object" else None,
             "alg_bytes_per_launch": alg_bytes,
             "nodes_per_ray": st["nodes"] / rays,
             "leaves_per_ray": st["leaves"] / rays,

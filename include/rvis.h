@@ -182,6 +182,14 @@ rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, const float *di
                          const rv_trace_params *p, int64_t *totals, void *ws, size_t ws_bytes,
                          void *stream);
 
+/*
+ * Copy `bytes` (a multiple of 16; 16-byte aligned pointers) from src to dst on
+ * `stream` with a grid-stride streaming kernel: the achievable-bandwidth probe
+ * for the roofline and the known-size reference for hardware byte counters.
+ * Errors: RV_ERR_INVALID_ARG (null or misaligned pointers, bad size), RV_ERR_HIP.
+ */
+rv_status rv_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Adjoint                                                                  */
 /* ------------------------------------------------------------------------ */

@@ -7,5 +7,5 @@ provides device memory and streams only.
 """
 from ._lib import RvError, load  # noqa: F401
 from .tracer import (BVH, Gaussians, TraceParams, build_bvh, trace_rays, trace_stats,  # noqa: F401
-                     trace_visibility, trace_visibility_backward)
+                     trace_visibility, trace_visibility_backward, stream_copy)
 from .autograd import VisibilityFn, visibility  # noqa: F401

@@ -65,6 +65,7 @@ SIGNATURES = {
     "rv_trace_rays": (_i32, [_vp, _PG, _vp, _i32, _PP, _vp, _i64, _vp, _vp]),
     "rv_trace_stats": (_i32, [_vp, _PG, _vp, _i32, _PP, _vp, _vp, _sz, _vp]),
     "rv_trace_visibility_backward": (_i32, [_vp, _PG, _vp, _i32, _PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rv_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
     "rv_surrogate_bytes": (_sz, []),
     "rv_surrogate_train_workspace_bytes": (_sz, [_i32]),
     "rv_surrogate_infer_workspace_bytes": (_sz, [_i64]),

@@ -196,10 +196,19 @@ __global__ __launch_bounds__(256) void k_leaf_prep(const float *__restrict__ mea
                                                    const float *__restrict__ log_scale,
                                                    const float *__restrict__ opacity, const float *__restrict__ normal,
                                                    int64_t n, const uint32_t *__restrict__ perm,
+                                                   const float *__restrict__ header,
                                                    float4 *__restrict__ rec, float *__restrict__ box,
                                                    float4 *__restrict__ origins) {
     int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
+    // scene scale: largest coordinate magnitude plus the diagonal of the means' box
+    float scale = 0.0f, diag2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        scale = fmaxf(scale, fmaxf(fabsf(header[a]), fabsf(header[3 + a])));
+        diag2 += (header[3 + a] - header[a]) * (header[3 + a] - header[a]);
+    }
+    const float widen_abs = (scale + sqrtf(diag2) + 1.0f) * 0x1p-20f;
     const int64_t i = perm[m];
     float qw = quat[4 * i], qx = quat[4 * i + 1], qy = quat[4 * i + 2], qz = quat[4 * i + 3];
     float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
@@ -228,13 +237,13 @@ __global__ __launch_bounds__(256) void k_leaf_prep(const float *__restrict__ mea
     rec[4 * m + 2] = make_float4(W[1][0], W[1][1], W[1][2], 0.0f);
     rec[4 * m + 3] = make_float4(W[2][0], W[2][1], W[2][2], 0.0f);
     // 3-sigma box: half extent along world axis a is 3 sqrt(sum_m (R_am s_m)^2),
-    // widened by a relative 2^-12 and by ~4 ulp of the coordinate so that a
-    // rounded box never cuts into the support
+    // widened by a relative 2^-12 (rounding of R, s and the square root) and by
+    // 2^-20 of the scene scale (rounding of the box and of the slab test)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float e0 = R[a][0] * s[0], e1 = R[a][1] * s[1], e2 = R[a][2] * s[2];
         float h = kBuildSigma * sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
-        h = h * (1.0f + 0x1p-12f) + fabsf(mu[a]) * 0x1p-21f + 0x1p-126f;
+        h = h * (1.0f + 0x1p-12f) + widen_abs;
         box[6 * m + a] = mu[a] - h;
         box[6 * m + 3 + a] = mu[a] + h;
     }
@@ -438,7 +447,7 @@ extern "C" rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
     if (st != RV_OK) return st;
 
     hipLaunchKernelGGL(k_leaf_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, g->mean, g->quat, g->log_scale,
-                       g->opacity, g->normal, n, perm, rec, box, orig);
+                       g->opacity, g->normal, n, perm, header, rec, box, orig);
     if (n > 1) {
         hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, keys, n,
                            reinterpret_cast<float4 *>(nodes), parent);

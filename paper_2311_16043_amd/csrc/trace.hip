@@ -7,7 +7,7 @@
 // order and one chunk of S consecutive directions; each lane traces its
 // Gaussian's S rays, one BVH node per loop iteration, and starts its next ray
 // as soon as the current one ends (lanes never wait on each other's rays).
-// Chunking gives ~4M lanes, so the hardware dispatcher balances the skewed
+// Chunking gives ~16M lanes, so the hardware dispatcher balances the skewed
 // per-ray work across many waves instead of waiting on the slowest Gaussian.
 // Blocks are renumbered so that each XCD (round-robin dispatch) walks a
 // contiguous range of the Morton order and its L2 sees a compact part of the
@@ -21,7 +21,7 @@ namespace {
 constexpr int kTraceBlock = 256;
 constexpr int kWavesPerBlock = kTraceBlock / 64;
 constexpr int kRing = 16;
-constexpr int64_t kTargetLanes = 4 << 20;
+constexpr int64_t kTargetLanes = 16 << 20;
 constexpr int kXcds = 8;
 
 struct Origin {
@@ -101,20 +101,22 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_chunks(const float4 *__re
     if (!lane_work(cm, m, chunk, k0, k1)) return;
     const Origin g = load_origin(rec, origins, m, c);
     RayState<kRing> rs;
+    int32_t spill[RingStack<kRing>::kSpill];
     rs.st.lds = lds + threadIdx.x;
+    rs.st.spill = spill;
     rs.st.stride = kTraceBlock;
     NoHit none;
     int64_t cn = 0, cl = 0, ch = 0;
     double sum = 0.0;
     int k = k0;
-    rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, cm.n);
+    rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, (int32_t)m, cm.n);
     while (true) {
         const bool done = rs.node < 0 || rs.template step<NoHit, kCount>(nodes, rec, c, none, &cn, &cl, &ch);
         if (done) {
             if (vis_ray) vis_ray[(int64_t)g.src * cm.K + k] = rs.T;
             sum += (double)rs.T;
             if (++k == k1) break;
-            rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, cm.n);
+            rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, (int32_t)m, cm.n);
         }
     }
     if (partial) partial[(int64_t)chunk * cm.n + g.src] = sum;
@@ -166,11 +168,13 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_list(const float4 *__rest
     f3 b1, b2;
     onb_duff(nrm, b1, b2);
     RayState<kRing> rs;
+    int32_t spill[RingStack<kRing>::kSpill];
     rs.st.lds = lds + threadIdx.x;
+    rs.st.spill = spill;
     rs.st.stride = kTraceBlock;
     NoHit none;
     rs.start(mk(mean[3 * i], mean[3 * i + 1], mean[3 * i + 2]), ray_direction(dirs, k, c.dir_mode, nrm, b1, b2),
-             c.tmin_scale * smax, (int32_t)i, n);
+             c.tmin_scale * smax, (int32_t)i, -1, n);
     while (rs.node >= 0 && !rs.step(nodes, rec, c, none)) {
     }
     out[s] = rs.T;
@@ -211,7 +215,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     const int K = cm.K;
     const Origin g = load_origin(rec, origins, m, c);
     RayState<kRing> rs;
+    int32_t spill[RingStack<kRing>::kSpill];
     rs.st.lds = lds + threadIdx.x;
+    rs.st.spill = spill;
     rs.st.stride = kTraceBlock;
     NoHit none;
     GradScatter gs;
@@ -231,7 +237,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
         }
         k = kk;
         if (k >= k1) return false;
-        rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, cm.n);
+        rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, (int32_t)m, cm.n);
         if (vis_fwd) {
             phase = 1;
             gs.g_over = -gk * vis_fwd[(int64_t)g.src * K + k];
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
             done = rs.node < 0 || rs.step(nodes, rec, c, none);
             if (done) {
                 gs.g_over = -gk * rs.T;
-                rs.start(rs.o, rs.d, rs.tmin, rs.self, cm.n);
+                rs.start(rs.o, rs.d, rs.tmin, rs.self, rs.self_leaf, cm.n);
                 phase = 1;
             }
         } else {

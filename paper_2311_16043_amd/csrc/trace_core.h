@@ -62,7 +62,9 @@ __device__ __forceinline__ f3 safe_inv(f3 d) {
 // Conservative slab test of the ray segment [t0, inf) against a box: the
 // differences are taken before scaling and the exit distance is enlarged by
 // (1 + 2 gamma_3) (Ize, "Robust BVH Ray Traversal", JCGT 2013), so a box the
-// exact ray enters is never rejected by rounding.
+// exact ray enters is never rejected by rounding. (The builder also widens
+// every leaf box by 2^-20 of the scene scale.) The FMA form lo/d - o/d saves
+// six instructions per box but costs registers and measured slower.
 __device__ __forceinline__ bool slab_hit(float lx, float ly, float lz, float hx, float hy, float hz, f3 o, f3 inv,
                                          float t0) {
     const float ax = (lx - o.x) * inv.x, bx = (hx - o.x) * inv.x;
@@ -93,13 +95,16 @@ struct NoHit {
 // Gaussians with the running T before this factor.
 template <class OnHit>
 __device__ __forceinline__ float leaf_factor(const float4 *__restrict__ rec, int32_t m, f3 o, f3 d, float tmin,
-                                             int32_t self, const Cuts &c, OnHit &on_hit, float T_before) {
-    const float4 r1 = rec[4 * m + 1];
-    const int32_t src = __float_as_int(r1.w);
-    if (src == self) return 1.0f;
+                                             int32_t self, int32_t self_leaf, const Cuts &c, OnHit &on_hit,
+                                             float T_before) {
+    if (m == self_leaf) return 1.0f;   // the source's own leaf, known by sorted position
+    // all four rows in flight at once
     const float4 r0 = rec[4 * m + 0];
+    const float4 r1 = rec[4 * m + 1];
     const float4 r2 = rec[4 * m + 2];
     const float4 r3 = rec[4 * m + 3];
+    const int32_t src = __float_as_int(r1.w);
+    if (src == self) return 1.0f;      // the source, when its sorted position is not known
     const f3 w0 = mk(r1.x, r1.y, r1.z), w1 = mk(r2.x, r2.y, r2.z), w2 = mk(r3.x, r3.y, r3.z);
     const f3 x = o - mk(r0.x, r0.y, r0.z);
     const f3 p = mk(dot(w0, x), dot(w1, x), dot(w2, x));
@@ -138,14 +143,16 @@ __device__ __forceinline__ float leaf_factor(const float4 *__restrict__ rec, int
 
 // LDS ring holding the top kRing stack entries of each lane (slot-major, so a
 // wave's lanes touch consecutive words for equal depths); deeper entries spill
-// to a private array. Invariant: entries [max(0, sp - kRing), sp) live in the
-// ring at slot (index % kRing), entries [0, sp - kRing) in spill[].
+// to a private array owned by the kernel (kept outside this struct so that the
+// scalar state stays in registers). Invariant: entries [max(0, sp - kRing), sp)
+// live in the ring at slot (index % kRing), entries [0, sp - kRing) in spill[].
 template <int kRing>
 struct RingStack {
+    static constexpr int kSpill = kMaxDepth - kRing;
     int32_t *lds;   // this lane's column: lds[slot * stride]
+    int32_t *spill; // private array of kSpill entries
     int stride;
     int sp;
-    int32_t spill[kMaxDepth - kRing];
 
     __device__ __forceinline__ void reset() { sp = 0; }
     __device__ __forceinline__ bool empty() const { return sp == 0; }
@@ -168,19 +175,21 @@ struct RingStack {
 // One ray's traversal state; step() processes one internal node.
 template <int kRing>
 struct RayState {
-    f3 o, d, inv;
+    f3 o, d, inv;   // origin, unit direction, 1/d
     float tmin, T;
-    int32_t self;
+    int32_t self;       // original index of the source Gaussian
+    int32_t self_leaf;  // its sorted leaf position, or -1 if unknown
     int32_t node;   // next internal node to visit, -1 when finished
     int64_t budget; // steps left: a ray visits each of the n-1 internal nodes at most once
     RingStack<kRing> st;
 
-    __device__ __forceinline__ void start(f3 o_, f3 d_, float tmin_, int32_t self_, int64_t n) {
+    __device__ __forceinline__ void start(f3 o_, f3 d_, float tmin_, int32_t self_, int32_t self_leaf_, int64_t n) {
         o = o_;
         d = d_;
         inv = safe_inv(d_);
         tmin = tmin_;
         self = self_;
+        self_leaf = self_leaf_;
         T = 1.0f;
         st.reset();
         node = n > 1 ? 0 : -1;   // a single Gaussian is the source itself
@@ -210,12 +219,12 @@ struct RayState {
         const bool hr = slab_hit(b.z, b.w, cc.x, cc.y, cc.z, cc.w, o, inv, tmin);
         if (kCount) ++*n_nodes;
         if (hl && left < 0) {
-            const float f = leaf_factor(rec, ~left, o, d, tmin, self, c, on_hit, T);
+            const float f = leaf_factor(rec, ~left, o, d, tmin, self, self_leaf, c, on_hit, T);
             if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
             T *= f;
         }
         if (hr && right < 0) {
-            const float f = leaf_factor(rec, ~right, o, d, tmin, self, c, on_hit, T);
+            const float f = leaf_factor(rec, ~right, o, d, tmin, self, self_leaf, c, on_hit, T);
             if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
             T *= f;
         }

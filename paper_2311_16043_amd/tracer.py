@@ -217,3 +217,11 @@ def trace_visibility_backward(bvh: BVH, g: Gaussians, dirs, params: TraceParams 
     _lib.call("rv_trace_visibility_backward", bvh.ptr, C.byref(gc), d.data_ptr(), K, C.byref(pc), p(grad_vis_ray),
               p(grad_vis_mean), p(vis_ray_fwd), go.data_ptr(), gm.data_ptr(), gl.data_ptr(), _stream_ptr(dev))
     return go, gm, gl
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """dst <- src (same byte size) with the library's streaming copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("stream_copy: size mismatch")
+    _lib.call("rv_stream_copy", src.data_ptr(), dst.data_ptr(), nbytes, _stream_ptr(src.device))

@@ -46,7 +46,10 @@ def check_build(scene, label=""):
     glo = A["leaf_boxes"][:, 0:3].astype(np.float64)
     ghi = A["leaf_boxes"][:, 3:6].astype(np.float64)
     assert np.all(glo <= olo) and np.all(ghi >= ohi), "a leaf box cuts into the 3-sigma support"
-    slack = 0.5 * (ohi - olo) * 1e-3 + 1e-6 * np.maximum(1.0, np.abs(olo))
+    # widening: 2^-12 relative plus 2^-20 of the scene scale (max |coord| + diagonal + 1)
+    lo_m, hi_m = O["lo"].astype(np.float64), O["hi"].astype(np.float64)
+    scale = max(np.abs(lo_m).max(), np.abs(hi_m).max()) + np.linalg.norm(hi_m - lo_m) + 1.0
+    slack = 0.5 * (ohi - olo) * 1e-3 + 2.0 ** -19 * scale + 1e-6 * np.abs(olo)
     assert np.all(olo - glo <= slack) and np.all(ghi - ohi <= slack), "leaf boxes not tight"
     if n > 1:
         # every child slot holds the child's own box: the leaf box, or the union

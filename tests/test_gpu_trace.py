@@ -161,3 +161,16 @@ def test_stats_are_consistent():
     ids = scenes.sample_ray_ids(20_000, 32, 2000, seed=5)
     orc = oracle.trace_rays(sc, dirs, 1, ids)
     print("hits/ray gpu", st["hits"] / rays, "oracle", orc["n_incl"].mean(), flush=True)
+
+
+def test_scene_far_from_the_origin():
+    """Coordinates near 100: binary32 ulps are 8e-6, so box tests and leaf tests
+    round much more coarsely; the result must still match the FP64 oracle."""
+    sc = scenes.make_object_scene(20_000, 1)
+    sc["mean"] = (sc["mean"].astype(np.float64) + np.array([97.0, -64.0, 33.0])).astype(np.float32)
+    dirs = scenes.fibonacci_dirs(32, True)
+    prm = TraceParams()
+    g, bvh, vr, vm = _run(sc, dirs, prm)
+    ids = scenes.sample_ray_ids(20_000, 32, 4096, seed=17)
+    orc = oracle.trace_rays(sc, dirs, 1, ids, _oprm(prm))
+    check_vis(vr.reshape(-1)[ids], orc, label="object-20k shifted")
