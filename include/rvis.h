@@ -221,69 +221,107 @@ rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaussians *g, c
 /* ------------------------------------------------------------------------ */
 
 /*
- * Network: input x (3, normalised to [-1, 1] by the scene box lo/hi stored in
- * the parameter blob) and unit direction d (3); each of the 6 scalars u is
- * encoded as [u, sin(2^l pi u), cos(2^l pi u)] for l = 0, 1, 2 (42 features,
+ * A learned stand-in for tracing the visibility term V of Eq. (9), trained on
+ * the tracer's own output, with the tracer as fallback.
+ *
+ * Network: input x (3, mapped to [-1, 1] by the box lo/hi stored in the
+ * parameter blob) and unit direction d (3); each of the 6 scalars u is encoded
+ * as [u, sin(2^l pi u), cos(2^l pi u)] for l = 0, 1, 2 (42 features,
  * zero-padded to 64); four hidden layers of 256 with ReLU (64->256, then
  * 3 x 256->256); a 256->2 head giving V = sigmoid(z0) and the predicted
- * absolute error u = softplus(z1). BF16 weights and activations into each
- * matrix product, FP32 accumulation, FP32 master weights and Adam state.
+ * absolute error U = softplus(z1). Matrix products run on the gfx950 matrix
+ * cores in BF16 (weights and layer inputs rounded to nearest even) with FP32
+ * accumulation; biases, nonlinearities, the loss, the master weights and Adam
+ * are FP32.
+ * Loss per sample: BCE(V, T) + |U - |T - V|| with V held constant in the
+ * second term. Parameters: one flat FP32 vector W1, b1, ..., W5, b5, each W
+ * stored [in][out] row-major (rv_surrogate_n_params() = 214,530 floats).
  */
 typedef struct rv_train_opts {
-    int64_t steps;      /* optimiser steps */
-    int32_t batch;      /* rows per step (multiple of 256) */
-    float lr;           /* Adam learning rate (peak) */
+    int64_t steps;       /* optimiser steps in this call */
+    int32_t batch;       /* samples per step (multiple of 128, <= the workspace's batch) */
+    float lr;            /* Adam step size at the start of the schedule */
     float beta1, beta2, eps;
-    float lr_min;       /* cosine decay floor */
-    uint64_t seed;      /* sample order */
-    int64_t step0;      /* global step of the first step (Adam bias correction, schedule) */
-    int64_t total_steps;/* schedule length */
+    float lr_min;        /* cosine-decay floor at step total_steps */
+    uint64_t seed;       /* sample draw: index = hash(seed, global step, slot) mod n_samples */
+    int64_t step0;       /* global index of this call's first step (Adam bias correction, schedule) */
+    int64_t total_steps; /* schedule length */
 } rv_train_opts;
 
-/* Bytes of the surrogate parameter blob (FP32 master + Adam m, v + BF16 copies + box). */
+/* Device pointers into a parameter blob (host-side arithmetic only). */
+typedef struct rv_surrogate_arrays {
+    float *header;   /* [16]: box lo[3], hi[3], ... */
+    float *master;   /* [n_params] FP32 weights */
+    float *adam_m;   /* [n_params] */
+    float *adam_v;   /* [n_params] */
+    void *packed;    /* BF16 copies laid out for the matrix cores */
+} rv_surrogate_arrays;
+
+/* Number of FP32 parameters (214,530). */
+int64_t rv_surrogate_n_params(void);
+
+/* Bytes of the parameter blob. */
 size_t rv_surrogate_bytes(void);
 
-/* Bytes of surrogate training scratch for a batch of `batch` rows. */
+/* rv_surrogate_arrays of a blob (no device access). */
+rv_status rv_surrogate_view(const void *params, rv_surrogate_arrays *out);
+
+/* Bytes of training scratch for batches of up to `batch` samples. */
 size_t rv_surrogate_train_workspace_bytes(int32_t batch);
 
-/* Bytes of inference scratch for q_count queries. */
+/* Bytes of inference scratch for q_count grid queries (fallback list). */
 size_t rv_surrogate_infer_workspace_bytes(int64_t q_count);
 
 /*
- * Initialise the parameter blob: weights with a seeded He-uniform draw
- * (counter-based hash of (seed, index)), biases 0, Adam state 0, and the
- * normalisation box lo[3], hi[3] (host floats).
+ * Initialise a blob (256-byte aligned, rv_surrogate_bytes()): the box
+ * lo[3]/hi[3] (host floats), the FP32 weights from `init_weights` (device,
+ * n_params floats, the flat order above) or, when it is NULL, a seeded
+ * He-uniform draw from a counter-based hash of (seed, index) with zero biases;
+ * Adam state zero; BF16 copies packed.
  */
 rv_status rv_surrogate_init(void *params, uint64_t seed, const float *box_lo_host, const float *box_hi_host,
-                            void *stream);
+                            const float *init_weights, void *stream);
 
 /*
- * Train on n_samples tracer samples: x [n][3], d [n][3], T [n]. Each step takes
- * `batch` sample indices from a seeded counter-based hash, runs the forward
- * pass, the loss BCE(V, T) + L1(u, |T - V| with V held constant), the backward
- * pass and one Adam step. loss_log [steps] (device, FP32; NULL to skip)
- * receives the mean loss of each step.
+ * Mean loss (loss_out, device float[1]) and its gradient (grad_out, device
+ * float[n_params], overwritten) on samples 0..n-1 of (x [n][3], d [n][3],
+ * T [n]); n <= the workspace's batch. Deterministic.
+ */
+rv_status rv_surrogate_loss_grad(const void *params, const float *x, const float *d, const float *T, int64_t n,
+                                 float *grad_out, float *loss_out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * o->steps Adam steps on batches drawn from n_samples tracer samples (x [n][3],
+ * d [n][3], T [n]). loss_log (device, FP32 [steps]; NULL to skip) receives
+ * each step's mean loss.
  */
 rv_status rv_surrogate_train(void *params, const float *x, const float *d, const float *T, int64_t n_samples,
-                             const rv_train_opts *o, float *loss_log, void *ws, size_t ws_bytes,
-                             void *stream);
+                             const rv_train_opts *o, float *loss_log, void *ws, size_t ws_bytes, void *stream);
 
 /* Free-form inference: vis[s], unc[s] (unc may be NULL) for n queries (x[s], d[s]). */
 rv_status rv_surrogate_infer_xd(const void *params, const float *x, const float *d, int64_t n, float *vis,
                                 float *unc, void *stream);
 
 /*
- * Grid inference over queries q in [q_begin, q_begin + q_count) with q = i*K + k
- * (x = mean_i, d = direction k of Gaussian i as in rv_trace_visibility).
- * vis[s] receives the surrogate's V; where its predicted error exceeds tau and
- * `bvh` is not NULL the query is traced instead (fallback) and vis[s] is the
- * tracer's T. unc (may be NULL) receives the predicted error; *n_fallback
- * (device int64) receives the number of traced queries.
+ * Grid inference over queries q in [q_begin, q_begin + q_count), q = i*K + k
+ * (x = mean_i, d = direction k of Gaussian i exactly as rv_trace_visibility
+ * forms it). vis[s] receives the surrogate's V, or the tracer's T where the
+ * predicted error U exceeds tau and `bvh` is not NULL (fallback; the same bits
+ * as rv_trace_rays for that ray). unc (may be NULL) receives U; *n_fallback
+ * (device int64) the number of traced queries. Queries are compacted with
+ * wave ballots into a list in `ws` and traced by a persistent kernel.
  */
 rv_status rv_surrogate_infer(const void *params, const void *bvh, const rv_gaussians *g, const float *dirs,
                              int32_t K, const rv_trace_params *p, int64_t q_begin, int64_t q_count, float tau,
                              float *vis, float *unc, int64_t *n_fallback, void *ws, size_t ws_bytes,
                              void *stream);
+
+/*
+ * Origin and unit direction of each listed ray (device, out_o/out_d [n][3]),
+ * formed exactly as the tracer forms them: the training inputs of the surrogate.
+ */
+rv_status rv_ray_setup(const rv_gaussians *g, const float *dirs, int32_t K, const rv_trace_params *p,
+                       const int64_t *ray_ids, int64_t n, float *out_o, float *out_d, void *stream);
 
 #ifdef __cplusplus
 }

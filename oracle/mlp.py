@@ -156,3 +156,20 @@ def adam_step(theta, m, v, g, step: int, lr: float, beta1=0.9, beta2=0.999, eps=
     mh = m / (1 - beta1 ** step)
     vh = v / (1 - beta2 ** step)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014; Vigna's constants)."""
+    x = (x + 0x9E3779B97F4A7C15) & _M64
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & _M64
+    return x ^ (x >> 31)
+
+
+def batch_indices(seed: int, step: int, batch: int, n_samples: int) -> np.ndarray:
+    """Training-sample indices of one step: splitmix64(seed ^ splitmix64(step * 2^32 + slot)) mod n."""
+    return np.array([splitmix64(seed ^ splitmix64(((step << 32) + s) & _M64)) % n_samples for s in range(batch)],
+                    dtype=np.int64)

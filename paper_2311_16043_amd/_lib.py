@@ -42,6 +42,11 @@ class RvTrainOpts(C.Structure):
                 ("step0", C.c_int64), ("total_steps", C.c_int64)]
 
 
+class RvSurrogateArrays(C.Structure):
+    _fields_ = [("header", C.c_void_p), ("master", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
+                ("packed", C.c_void_p)]
+
+
 class RvError(RuntimeError):
     def __init__(self, fn: str, code: int, msg: str):
         super().__init__(f"{fn} failed with status {code}: {msg}")
@@ -66,14 +71,18 @@ SIGNATURES = {
     "rv_trace_stats": (_i32, [_vp, _PG, _vp, _i32, _PP, _vp, _vp, _sz, _vp]),
     "rv_trace_visibility_backward": (_i32, [_vp, _PG, _vp, _i32, _PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rv_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
+    "rv_surrogate_n_params": (_i64, []),
     "rv_surrogate_bytes": (_sz, []),
+    "rv_surrogate_view": (_i32, [_vp, C.POINTER(RvSurrogateArrays)]),
     "rv_surrogate_train_workspace_bytes": (_sz, [_i32]),
     "rv_surrogate_infer_workspace_bytes": (_sz, [_i64]),
-    "rv_surrogate_init": (_i32, [_vp, C.c_uint64, _vp, _vp, _vp]),
+    "rv_surrogate_init": (_i32, [_vp, C.c_uint64, _vp, _vp, _vp, _vp]),
+    "rv_surrogate_loss_grad": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     "rv_surrogate_train": (_i32, [_vp, _vp, _vp, _vp, _i64, C.POINTER(RvTrainOpts), _vp, _vp, _sz, _vp]),
     "rv_surrogate_infer_xd": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "rv_surrogate_infer": (_i32, [_vp, _vp, _PG, _vp, _i32, _PP, _i64, _i64, _f, _vp, _vp, _vp, _vp, _sz,
                                   _vp]),
+    "rv_ray_setup": (_i32, [_PG, _vp, _i32, _PP, _vp, _i64, _vp, _vp, _vp]),
 }
 
 _lib = None

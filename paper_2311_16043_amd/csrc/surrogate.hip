@@ -1,28 +1,921 @@
-// surrogate.hip -- MLP visibility surrogate (placeholder entry points).
-#include "rv_internal.h"
+// surrogate.hip -- MLP visibility surrogate on the gfx950 matrix cores.
+//
+// Every product runs as v_mfma_f32_16x16x32_bf16 in the transposed form
+//   C[16 outputs x 16 samples] += A[16 outputs x 32 inputs] * B[32 inputs x 16 samples],
+// so that the accumulator layout (lane = one sample, four consecutive outputs)
+// is reused unchanged as the next product's B operand: a matrix product is
+// invariant under a common permutation of its summation index, so the packed
+// weights (A operands) are laid out in the order in which the previous layer
+// leaves its outputs in the lanes (kfeat below). Activations of a 32-sample
+// wave never leave registers in inference.
+//
+// Parameter blob: header | FP32 master | Adam m | Adam v | BF16 forward A
+// operands | BF16 backward A operands (W used as [in x out] for the
+// gradient through the layer).
+#include "trace_core.h"
+
+namespace rv {
+namespace {
+
+constexpr int kHid = 256, kIn = 64, kEnc = 42;
+constexpr int64_t kNParams = 214530;
+__host__ __device__ constexpr int64_t off_w(int l) {  // l = 0..4 (layers 1..5)
+    return l == 0 ? 0 : l == 1 ? 16640 : l == 2 ? 82432 : l == 3 ? 148224 : 214016;
+}
+__host__ __device__ constexpr int64_t off_b(int l) {
+    return l == 0 ? 16384 : l == 1 ? 82176 : l == 2 ? 147968 : l == 3 ? 213760 : 214528;
+}
+__host__ __device__ constexpr int n_in(int l) { return l == 0 ? kIn : kHid; }
+__host__ __device__ constexpr int n_out(int l) { return l == 4 ? 2 : kHid; }
+// packed A operands, in bf16 elements: forward layer l = 0..4
+__host__ __device__ constexpr int64_t fwd_off(int l) {
+    return l == 0 ? 0 : l == 1 ? 16384 : l == 2 ? 81920 : l == 3 ? 147456 : 212992;
+}
+constexpr int64_t kFwdTotal = 217088;
+// backward A operands: j = 0 for W5, 1 for W4, 2 for W3, 3 for W2
+__host__ __device__ constexpr int64_t bwd_off(int j) { return j == 0 ? 0 : j == 1 ? 8192 : j == 2 ? 73728 : 139264; }
+constexpr int64_t kBwdTotal = 204800;
+
+struct SurLayout {
+    size_t header, master, m, v, fwd, bwd, total;
+};
+inline SurLayout sur_layout() {
+    SurLayout L{};
+    size_t off = 0;
+    L.header = off; off = align_up(off + 64 * sizeof(float));
+    L.master = off; off = align_up(off + kNParams * sizeof(float));
+    L.m = off; off = align_up(off + kNParams * sizeof(float));
+    L.v = off; off = align_up(off + kNParams * sizeof(float));
+    L.fwd = off; off = align_up(off + kFwdTotal * 2);
+    L.bwd = off; off = align_up(off + kBwdTotal * 2);
+    L.total = off;
+    return L;
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+// bfloat16 bits of x, round to nearest even (finite inputs)
+__host__ __device__ __forceinline__ uint32_t bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
+__device__ __forceinline__ float bf16_val(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+// Feature carried by slot s (0..7) of lane group g (lane / 16) in k-block kb of
+// a B operand built from accumulators: blocks 2kb and 2kb+1 of 16 outputs,
+// four consecutive outputs per lane group.
+__host__ __device__ constexpr int kfeat(int kb, int g, int s) { return (2 * kb + (s >> 2)) * 16 + 4 * g + (s & 3); }
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+// ---- encoding -----------------------------------------------------------------
+
+// Feature f of the encoding of u[0..5]: u, sin(pi u), cos(pi u), sin(2 pi u),
+// cos(2 pi u), sin(4 pi u), cos(4 pi u) for each scalar; 0 for f >= 42.
+__device__ __forceinline__ float enc_feature(int f, float u0, float u1, float u2, float u3, float u4, float u5) {
+    if (f >= kEnc) return 0.0f;
+    const int a = f / 7, c = f - 7 * a;
+    const float v = a == 0 ? u0 : a == 1 ? u1 : a == 2 ? u2 : a == 3 ? u3 : a == 4 ? u4 : u5;
+    if (c == 0) return v;
+    const int lvl = (c - 1) >> 1;
+    const float w = 3.14159265358979323846f * (float)(1 << lvl);
+    return (c & 1) ? __sinf(w * v) : __cosf(w * v);
+}
+
+// ---- forward -----------------------------------------------------------------------
+
+enum FwdMode { kModeXd = 0, kModeGrid = 1, kModeTrain = 2 };
+
+struct FwdArgs {
+    const float *master;
+    const u32x4 *fwd;
+    const float *header;
+    int64_t n;               // samples (queries) in this launch
+    // explicit inputs (xd and train)
+    const float *x, *d, *T;
+    // training: sample draw and saved tensors
+    int hashed;              // 1: sample index = hash(seed, step, s) mod n_samples
+    int64_t n_samples;
+    uint64_t seed;
+    int64_t step;
+    uint16_t *ht;            // activations, feature-major: section j at ht + ht_off(j) * stride
+    int64_t stride;          // samples per feature row (>= padded n)
+    uint16_t *dz5;           // [2][stride]
+    float *loss_part;        // per wave
+    // outputs
+    float *vis, *unc;
+    // grid queries
+    const float *gmean, *gnormal, *dirs;
+    int K, dir_mode;
+    int64_t q_begin;
+    float tau;
+    int64_t *fb_list;
+    unsigned long long *fb_count;
+};
+
+// feature-major activation sections: HT0 (64 rows), HT1..HT4 (256 rows each)
+__host__ __device__ constexpr int64_t ht_row(int j) { return j == 0 ? 0 : 64 + (int64_t)(j - 1) * 256; }
+constexpr int64_t kHtRows = 64 + 4 * 256;
+constexpr int64_t kDzRows = 4 * 256 + 16;  // dZ1..dZ4 (256 rows each), dZ5 (2 rows, 16 reserved)
+__host__ __device__ constexpr int64_t dz_row(int l) { return l < 4 ? (int64_t)l * 256 : 1024; }  // l = 0..4
+
+// One hidden layer: act (B operands, kb-blocks of the input) -> act (the
+// ReLU outputs, as B operands of the next layer).
+template <int KB>
+__device__ __forceinline__ void hidden_layer(const u32x4 *__restrict__ A, const float *__restrict__ bias,
+                                             u32x4 (&act)[8][2], int lane) {
+    f32x4 acc[16][2];
+#pragma unroll
+    for (int ob = 0; ob < 16; ++ob)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[ob][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+        for (int ob = 0; ob < 16; ++ob) {
+            const u32x4 a = A[(ob * KB + kb) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[ob][nt] = mfma16(a, act[kb][nt], acc[ob][nt]);
+        }
+    }
+    const int g = lane >> 4;
+#pragma unroll
+    for (int ob = 0; ob < 16; ++ob) {
+        const float4 bv = *reinterpret_cast<const float4 *>(bias + ob * 16 + 4 * g);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const float h0 = fmaxf(acc[ob][nt][0] + bv.x, 0.f), h1 = fmaxf(acc[ob][nt][1] + bv.y, 0.f);
+            const float h2 = fmaxf(acc[ob][nt][2] + bv.z, 0.f), h3 = fmaxf(acc[ob][nt][3] + bv.w, 0.f);
+            act[ob >> 1][nt][(ob & 1) * 2 + 0] = pack2(h0, h1);
+            act[ob >> 1][nt][(ob & 1) * 2 + 1] = pack2(h2, h3);
+        }
+    }
+}
+
+// Store the B-operand blocks [0, KB) of act as feature-major rows of ht.
+template <int KB>
+__device__ __forceinline__ void store_act(uint16_t *__restrict__ ht, int64_t stride, const u32x4 (&act)[8][2],
+                                          int lane, int64_t s_base, int64_t n) {
+    const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int64_t s = s_base + nt * 16 + col;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int sl = 0; sl < 8; ++sl) {
+                const uint32_t w = act[kb][nt][sl >> 1];
+                const uint16_t b = (uint16_t)((sl & 1) ? (w >> 16) : (w & 0xffffu));
+                ht[(int64_t)kfeat(kb, g, sl) * stride + s] = s < n ? b : (uint16_t)0;
+            }
+    }
+}
+
+template <int kMode>
+__global__ __launch_bounds__(256) void k_mlp_forward(FwdArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t s_base = wave * 32;
+    if (s_base >= a.n) return;  // wave-uniform
+    const int g = lane >> 4, col = lane & 15;
+    const float lo0 = a.header[0], lo1 = a.header[1], lo2 = a.header[2];
+    const float hi0 = a.header[3], hi1 = a.header[4], hi2 = a.header[5];
+    auto nrm = [](float x, float lo, float hi) {
+        const float span = hi - lo;
+        return span > 0.f ? 2.0f * (x - lo) / span - 1.0f : 0.0f;
+    };
+
+    u32x4 act[8][2];
+    float Tv[2] = {0.f, 0.f};
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int64_t s = s_base + nt * 16 + col;
+        const bool valid = s < a.n;
+        float x0 = 0.f, x1 = 0.f, x2 = 0.f, d0 = 0.f, d1 = 0.f, d2 = 1.f;
+        if (valid) {
+            if (kMode == kModeGrid) {
+                const int64_t q = a.q_begin + s;
+                const int64_t i = q / a.K;
+                const int k = (int)(q - i * a.K);
+                float nx = 0.f, ny = 0.f, nz = 1.f;
+                if (a.gnormal) {
+                    nx = a.gnormal[3 * i]; ny = a.gnormal[3 * i + 1]; nz = a.gnormal[3 * i + 2];
+                    const float nl = sqrtf(nx * nx + ny * ny + nz * nz);
+                    nx /= nl; ny /= nl; nz /= nl;
+                }
+                f3 b1, b2;
+                const f3 nv = mk(nx, ny, nz);
+                onb_duff(nv, b1, b2);
+                const f3 dv = ray_direction(a.dirs, k, a.dir_mode, nv, b1, b2);
+                x0 = a.gmean[3 * i]; x1 = a.gmean[3 * i + 1]; x2 = a.gmean[3 * i + 2];
+                d0 = dv.x; d1 = dv.y; d2 = dv.z;
+            } else {
+                int64_t idx = s;
+                if (kMode == kModeTrain && a.hashed)
+                    idx = (int64_t)(splitmix64(a.seed ^ splitmix64((uint64_t)a.step * 0x100000000ull + (uint64_t)s)) %
+                                    (uint64_t)a.n_samples);
+                x0 = a.x[3 * idx]; x1 = a.x[3 * idx + 1]; x2 = a.x[3 * idx + 2];
+                d0 = a.d[3 * idx]; d1 = a.d[3 * idx + 1]; d2 = a.d[3 * idx + 2];
+                if (kMode == kModeTrain) Tv[nt] = a.T[idx];
+            }
+        }
+        const float u0 = nrm(x0, lo0, hi0), u1 = nrm(x1, lo1, hi1), u2 = nrm(x2, lo2, hi2);
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                act[kb][nt][w] = pack2(enc_feature(kfeat(kb, g, 2 * w), u0, u1, u2, d0, d1, d2),
+                                       enc_feature(kfeat(kb, g, 2 * w + 1), u0, u1, u2, d0, d1, d2));
+    }
+    if (kMode == kModeTrain) store_act<2>(a.ht + ht_row(0) * a.stride, a.stride, act, lane, s_base, a.n);
+
+    const float *master = a.master;
+    hidden_layer<2>(a.fwd + fwd_off(0) / 8, master + off_b(0), act, lane);
+    if (kMode == kModeTrain) store_act<8>(a.ht + ht_row(1) * a.stride, a.stride, act, lane, s_base, a.n);
+    hidden_layer<8>(a.fwd + fwd_off(1) / 8, master + off_b(1), act, lane);
+    if (kMode == kModeTrain) store_act<8>(a.ht + ht_row(2) * a.stride, a.stride, act, lane, s_base, a.n);
+    hidden_layer<8>(a.fwd + fwd_off(2) / 8, master + off_b(2), act, lane);
+    if (kMode == kModeTrain) store_act<8>(a.ht + ht_row(3) * a.stride, a.stride, act, lane, s_base, a.n);
+    hidden_layer<8>(a.fwd + fwd_off(3) / 8, master + off_b(3), act, lane);
+    if (kMode == kModeTrain) store_act<8>(a.ht + ht_row(4) * a.stride, a.stride, act, lane, s_base, a.n);
+
+    // head: one block of 16 outputs, rows 0 and 1 are z0, z1
+    f32x4 acc5[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    const u32x4 *A5 = a.fwd + fwd_off(4) / 8;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+        const u32x4 av = A5[kb * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc5[nt] = mfma16(av, act[kb][nt], acc5[nt]);
+    }
+    const float b50 = master[off_b(4)], b51 = master[off_b(4) + 1];
+    float lsum = 0.f;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int64_t s = s_base + nt * 16 + col;
+        const bool valid = s < a.n;
+        const float z0 = acc5[nt][0] + b50, z1 = acc5[nt][1] + b51;
+        const float V = 1.0f / (1.0f + expf(-z0));
+        const float U = fmaxf(z1, 0.f) + log1pf(expf(-fabsf(z1)));
+        if (kMode != kModeTrain) {
+            const bool fb = g == 0 && valid && a.fb_list && U > a.tau;
+            if (g == 0 && valid) {
+                a.vis[s] = V;
+                if (a.unc) a.unc[s] = U;
+            }
+            if (kMode == kModeGrid) {
+                const uint64_t m = __ballot(fb);
+                if (m) {
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(a.fb_count, (unsigned long long)__popcll(m));
+                    base = __shfl(base, 0);
+                    if (fb) a.fb_list[base + __popcll(m & ((1ull << lane) - 1ull))] = s;
+                }
+            }
+        } else {
+            const float T = Tv[nt];
+            const float e = fabsf(T - V);
+            const float inv_n = 1.0f / (float)a.n;
+            const float dz0 = (V - T) * inv_n;
+            const float sg = (U > e) ? 1.f : (U < e) ? -1.f : 0.f;
+            const float dz1 = sg * (1.0f / (1.0f + expf(-z1))) * inv_n;
+            if (g == 0) {
+                a.dz5[s] = valid ? (uint16_t)bf16_bits(dz0) : (uint16_t)0;
+                a.dz5[a.stride + s] = valid ? (uint16_t)bf16_bits(dz1) : (uint16_t)0;
+                if (valid) {
+                    const float bce = -(T * logf(fmaxf(V, 1e-12f)) + (1.f - T) * logf(fmaxf(1.f - V, 1e-12f)));
+                    lsum += bce + fabsf(U - e);
+                }
+            }
+        }
+    }
+    if (kMode == kModeTrain) {
+        for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+        if (lane == 0) a.loss_part[wave] = lsum;
+    }
+}
+
+// ---- backward through the layers ----------------------------------------------
+
+// dH = W dZ for one layer (A = its backward operands, KB k-blocks of the
+// output gradient), then the ReLU mask of the layer's input (feature-major
+// rows ht_in) gives the pre-activation gradient of the layer below, stored
+// feature-major (dz_out) and kept as B operands in act.
+template <int KB>
+__device__ __forceinline__ void dgrad_layer(const u32x4 *__restrict__ A, const uint16_t *__restrict__ ht_in,
+                                            uint16_t *__restrict__ dz_out, int64_t stride, u32x4 (&act)[8][2],
+                                            int lane, int64_t s_base, int64_t n) {
+    f32x4 acc[16][2];
+#pragma unroll
+    for (int mb = 0; mb < 16; ++mb)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mb][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+        for (int mb = 0; mb < 16; ++mb) {
+            const u32x4 av = A[(mb * KB + kb) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[mb][nt] = mfma16(av, act[kb][nt], acc[mb][nt]);
+        }
+    }
+    const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int64_t s = s_base + nt * 16 + col;
+        const bool valid = s < n;
+#pragma unroll
+        for (int mb = 0; mb < 16; ++mb) {
+            float z[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t f = mb * 16 + 4 * g + r;
+                const bool on = valid && ht_in[f * stride + s] != 0;   // bf16 ReLU output > 0
+                z[r] = on ? acc[mb][nt][r] : 0.0f;
+                dz_out[f * stride + s] = (uint16_t)bf16_bits(z[r]);
+            }
+            act[mb >> 1][nt][(mb & 1) * 2 + 0] = pack2(z[0], z[1]);
+            act[mb >> 1][nt][(mb & 1) * 2 + 1] = pack2(z[2], z[3]);
+        }
+    }
+}
+
+struct BwdArgs {
+    const u32x4 *bwd;
+    const uint16_t *ht;
+    uint16_t *dz;
+    int64_t stride;
+    int64_t n;
+};
+
+__global__ __launch_bounds__(256) void k_mlp_backward(BwdArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t s_base = wave * 32;
+    if (s_base >= a.n) return;
+    const int g = lane >> 4, col = lane & 15;
+    u32x4 act[8][2];
+    // head gradient as a B operand: outputs 0 and 1 sit in slots 0, 1 of lane group 0
+    const uint16_t *dz5 = a.dz + dz_row(4) * a.stride;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int64_t s = s_base + nt * 16 + col;
+        act[0][nt] = u32x4{0u, 0u, 0u, 0u};
+        if (g == 0) act[0][nt][0] = (uint32_t)dz5[s] | ((uint32_t)dz5[a.stride + s] << 16);
+    }
+    dgrad_layer<1>(a.bwd + bwd_off(0) / 8, a.ht + ht_row(4) * a.stride, a.dz + dz_row(3) * a.stride, a.stride, act,
+                   lane, s_base, a.n);
+    dgrad_layer<8>(a.bwd + bwd_off(1) / 8, a.ht + ht_row(3) * a.stride, a.dz + dz_row(2) * a.stride, a.stride, act,
+                   lane, s_base, a.n);
+    dgrad_layer<8>(a.bwd + bwd_off(2) / 8, a.ht + ht_row(2) * a.stride, a.dz + dz_row(1) * a.stride, a.stride, act,
+                   lane, s_base, a.n);
+    dgrad_layer<8>(a.bwd + bwd_off(3) / 8, a.ht + ht_row(1) * a.stride, a.dz + dz_row(0) * a.stride, a.stride, act,
+                   lane, s_base, a.n);
+}
+
+// ---- weight gradients ----------------------------------------------------------------
+
+// One wave: a 64 x 64 tile of dW_l[k][o] = sum_s h[k][s] dz[o][s] over one
+// slice of the batch (C[k][o] += A[k x 32 samples] B[32 samples x o]), plus the
+// bias gradient of its 64 outputs when it holds the first k-tile.
+struct WgradArgs {
+    const uint16_t *ht, *dz;
+    int64_t stride;
+    int64_t n_pad;       // samples rounded up to 32
+    int64_t slice_len;   // multiple of 32
+    int n_slices;
+    float *partial;      // [n_slices][n_params]
+};
+
+// tiles per layer: l0: 1 x 4, l1-3: 4 x 4, l4: 4 x 1 -> 56
+__device__ __forceinline__ void tile_of(int t, int &l, int &kt, int &ot) {
+    if (t < 4) { l = 0; kt = 0; ot = t; return; }
+    t -= 4;
+    if (t < 48) { l = 1 + t / 16; kt = (t % 16) / 4; ot = t % 4; return; }
+    t -= 48;
+    l = 4; kt = t; ot = 0;
+}
+constexpr int kTiles = 56;
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad(WgradArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= (int64_t)kTiles * a.n_slices) return;
+    const int tile = (int)(wave % kTiles);
+    const int slice = (int)(wave / kTiles);
+    int l, kt, ot;
+    tile_of(tile, l, kt, ot);
+    const int Nout = n_out(l);
+    const int g = lane >> 4, col = lane & 15;
+    const uint16_t *H = a.ht + ht_row(l) * a.stride;
+    const uint16_t *D = a.dz + dz_row(l) * a.stride;
+    const int64_t s0 = (int64_t)slice * a.slice_len;
+    const int64_t s1 = min(a.n_pad, s0 + a.slice_len);
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t s = s0; s < s1; s += 32) {
+        u32x4 av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t k = (int64_t)kt * 64 + i * 16 + col;
+            av[i] = *reinterpret_cast<const u32x4 *>(H + k * a.stride + s + 8 * g);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = ot * 64 + j * 16 + col;
+            if (o < Nout) {
+                bv[j] = *reinterpret_cast<const u32x4 *>(D + (int64_t)o * a.stride + s + 8 * g);
+            } else {
+                bv[j] = u32x4{0u, 0u, 0u, 0u};
+            }
+            if (kt == 0) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    bsum[j] += bf16_val(bv[j][w] & 0xffffu) + bf16_val(bv[j][w] >> 16);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+    }
+    float *P = a.partial + (int64_t)slice * kNParams;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = ot * 64 + j * 16 + col;
+            if (o < Nout) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = kt * 64 + i * 16 + 4 * g + r;
+                    P[off_w(l) + (int64_t)k * Nout + o] = acc[i][j][r];
+                }
+            }
+        }
+    if (kt == 0) {
+        // lanes col, col+16, col+32, col+48 hold the same output: add the four groups in a fixed order
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float v = bsum[j];
+            const float v1 = __shfl(v, col + 16), v2 = __shfl(v, col + 32), v3 = __shfl(v, col + 48);
+            const float v0 = __shfl(v, col);
+            const int o = ot * 64 + j * 16 + col;
+            if (g == 0 && o < Nout) P[off_b(l) + o] = ((v0 + v1) + v2) + v3;
+        }
+    }
+}
+
+// grad[p] = sum over slices (in order) of partial[slice][p]; loss = sum of wave partials / n
+__global__ __launch_bounds__(256) void k_reduce_grad(const float *__restrict__ partial, int n_slices,
+                                                     float *__restrict__ grad, const float *__restrict__ loss_part,
+                                                     int64_t n_waves, int64_t n, float *__restrict__ loss_out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kNParams) {
+        float s = 0.f;
+        for (int i = 0; i < n_slices; ++i) s += partial[(int64_t)i * kNParams + p];
+        grad[p] = s;
+    }
+    if (p == 0 && loss_out) {
+        double s = 0.0;
+        for (int64_t w = 0; w < n_waves; ++w) s += loss_part[w];
+        *loss_out = (float)(s / (double)n);
+    }
+}
+
+// ---- optimiser and packing ---------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                              const float *__restrict__ grad, float lr, float beta1, float beta2,
+                                              float eps, float c1, float c2) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNParams) return;
+    const float gr = grad[p];
+    const float mm = beta1 * m[p] + (1.f - beta1) * gr;
+    const float vv = beta2 * v[p] + (1.f - beta2) * gr * gr;
+    m[p] = mm;
+    v[p] = vv;
+    w[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// BF16 A operands from the FP32 master weights (see kfeat).
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ master, uint16_t *__restrict__ fwd,
+                                              uint16_t *__restrict__ bwd) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < kFwdTotal) {
+        int l = 0;
+        while (l < 4 && e >= fwd_off(l + 1)) ++l;
+        const int64_t r = e - fwd_off(l);
+        const int KB = n_in(l) / 32;
+        const int s = (int)(r & 7), lane = (int)((r >> 3) & 63);
+        const int64_t blk = r >> 9;
+        const int kb = (int)(blk % KB), ob = (int)(blk / KB);
+        const int o = ob * 16 + (lane & 15), k = kfeat(kb, lane >> 4, s);
+        const float w = (o < n_out(l)) ? master[off_w(l) + (int64_t)k * n_out(l) + o] : 0.0f;
+        fwd[e] = (uint16_t)bf16_bits(w);
+    } else if (e < kFwdTotal + kBwdTotal) {
+        const int64_t eb = e - kFwdTotal;
+        int j = 0;
+        while (j < 3 && eb >= bwd_off(j + 1)) ++j;
+        const int l = 4 - j;  // layer index of the weights
+        const int64_t r = eb - bwd_off(j);
+        const int KB = (l == 4) ? 1 : 8;
+        const int s = (int)(r & 7), lane = (int)((r >> 3) & 63);
+        const int64_t blk = r >> 9;
+        const int kb = (int)(blk % KB), mb = (int)(blk / KB);
+        const int k = mb * 16 + (lane & 15), o = kfeat(kb, lane >> 4, s);
+        const float w = (o < n_out(l)) ? master[off_w(l) + (int64_t)k * n_out(l) + o] : 0.0f;
+        bwd[eb] = (uint16_t)bf16_bits(w);
+    }
+}
+
+// He-uniform from a counter-based hash, zero biases.
+__global__ __launch_bounds__(256) void k_init_hash(float *__restrict__ master, uint64_t seed) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNParams) return;
+    int l = 0;
+    while (l < 4 && p >= off_w(l + 1)) ++l;
+    if (p >= off_b(l)) {
+        master[p] = 0.0f;
+        return;
+    }
+    const float lim = sqrtf(6.0f / (float)n_in(l));
+    const uint64_t h = splitmix64(seed ^ splitmix64((uint64_t)p));
+    const float u = (float)(h >> 40) * (1.0f / 16777216.0f);  // [0, 1)
+    master[p] = (2.0f * u - 1.0f) * lim;
+}
+
+__global__ __launch_bounds__(256) void k_copy_f32(const float *__restrict__ src, float *__restrict__ dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float *__restrict__ p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(64) void k_set_header(float *__restrict__ h, float l0, float l1, float l2, float h0,
+                                                   float h1, float h2) {
+    if (threadIdx.x == 0) {
+        h[0] = l0; h[1] = l1; h[2] = l2; h[3] = h0; h[4] = h1; h[5] = h2;
+        for (int i = 6; i < 64; ++i) h[i] = 0.0f;
+    }
+}
+
+// ---- fallback tracing and ray setup -----------------------------------------------------------------
+
+constexpr int kFbRing = 16;
+
+// Persistent grid-stride loop over the compacted fallback list.
+__global__ __launch_bounds__(256) void k_fallback_trace(const float4 *__restrict__ nodes, const float4 *__restrict__ rec,
+                                                        const float *__restrict__ mean, const float *__restrict__ normal,
+                                                        const float *__restrict__ log_scale, int64_t n,
+                                                        const float *__restrict__ dirs, int K, Cuts c, int64_t q_begin,
+                                                        const int64_t *__restrict__ list,
+                                                        const unsigned long long *__restrict__ count,
+                                                        float *__restrict__ vis, int64_t *__restrict__ n_fallback) {
+    __shared__ int32_t lds[kFbRing * 256];
+    const int64_t cnt = (int64_t)*count;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_fallback) *n_fallback = cnt;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += stride) {
+        const int64_t s = list[j];
+        const int64_t r = q_begin + s;
+        const int64_t i = r / K;
+        const int k = (int)(r - i * K);
+        float nx = 0.f, ny = 0.f, nz = 1.f;
+        if (normal) {
+            nx = normal[3 * i]; ny = normal[3 * i + 1]; nz = normal[3 * i + 2];
+            const float nl = sqrtf(nx * nx + ny * ny + nz * nz);
+            nx /= nl; ny /= nl; nz /= nl;
+        }
+        const float smax = expf(fmaxf(log_scale[3 * i], fmaxf(log_scale[3 * i + 1], log_scale[3 * i + 2])));
+        const f3 nrm = mk(nx, ny, nz);
+        f3 b1, b2;
+        onb_duff(nrm, b1, b2);
+        RayState<kFbRing> rs;
+        int32_t spill[RingStack<kFbRing>::kSpill];
+        rs.st.lds = lds + threadIdx.x;
+        rs.st.spill = spill;
+        rs.st.stride = 256;
+        NoHit none;
+        rs.start(mk(mean[3 * i], mean[3 * i + 1], mean[3 * i + 2]), ray_direction(dirs, k, c.dir_mode, nrm, b1, b2),
+                 c.tmin_scale * smax, (int32_t)i, -1, n);
+        while (rs.node >= 0 && !rs.step(nodes, rec, c, none)) {
+        }
+        vis[s] = rs.T;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ray_setup(const float *__restrict__ mean, const float *__restrict__ normal,
+                                                   int64_t n, const float *__restrict__ dirs, int K, int dir_mode,
+                                                   const int64_t *__restrict__ ids, int64_t n_rays,
+                                                   float *__restrict__ out_o, float *__restrict__ out_d) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_rays) return;
+    const int64_t r = ids[s];
+    if (r < 0 || r >= n * (int64_t)K) {
+        const float nan = __int_as_float(0x7fc00000);
+        for (int a = 0; a < 3; ++a) out_o[3 * s + a] = out_d[3 * s + a] = nan;
+        return;
+    }
+    const int64_t i = r / K;
+    const int k = (int)(r - i * K);
+    float nx = 0.f, ny = 0.f, nz = 1.f;
+    if (normal) {
+        nx = normal[3 * i]; ny = normal[3 * i + 1]; nz = normal[3 * i + 2];
+        const float nl = sqrtf(nx * nx + ny * ny + nz * nz);
+        nx /= nl; ny /= nl; nz /= nl;
+    }
+    const f3 nrm = mk(nx, ny, nz);
+    f3 b1, b2;
+    onb_duff(nrm, b1, b2);
+    const f3 d = ray_direction(dirs, k, dir_mode, nrm, b1, b2);
+    out_o[3 * s] = mean[3 * i]; out_o[3 * s + 1] = mean[3 * i + 1]; out_o[3 * s + 2] = mean[3 * i + 2];
+    out_d[3 * s] = d.x; out_d[3 * s + 1] = d.y; out_d[3 * s + 2] = d.z;
+}
+
+// ---- training workspace --------------------------------------------------------------------------------
+
+constexpr int64_t kSliceLen = 1024;
+
+struct TrainWs {
+    size_t ht, dz, partial, grad, loss_part, loss, total;
+    int64_t stride, n_slices, n_waves;
+};
+
+inline TrainWs train_ws(int64_t batch) {
+    TrainWs W{};
+    const int64_t pad = ((batch + 127) / 128) * 128;
+    W.stride = pad;
+    W.n_slices = (pad + kSliceLen - 1) / kSliceLen;
+    W.n_waves = pad / 32;
+    size_t off = 0;
+    W.ht = off; off = align_up(off + (size_t)kHtRows * pad * 2);
+    W.dz = off; off = align_up(off + (size_t)kDzRows * pad * 2);
+    W.partial = off; off = align_up(off + (size_t)W.n_slices * kNParams * 4);
+    W.grad = off; off = align_up(off + (size_t)kNParams * 4);
+    W.loss_part = off; off = align_up(off + (size_t)W.n_waves * 4);
+    W.loss = off; off = align_up(off + 256);
+    W.total = off;
+    return W;
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// forward (train) + backward + weight gradients + reduction on samples [0, n)
+rv_status loss_grad_impl(const void *params, const float *x, const float *d, const float *T, int64_t n, bool hashed,
+                         int64_t n_samples, uint64_t seed, int64_t step, float *grad, float *loss_out, void *ws,
+                         const TrainWs &W, hipStream_t s) {
+    const SurLayout L = sur_layout();
+    const int64_t n_pad = ((n + 31) / 32) * 32;
+    FwdArgs fa{};
+    fa.master = at<float>(params, L.master);
+    fa.fwd = at<u32x4>(params, L.fwd);
+    fa.header = at<float>(params, L.header);
+    fa.n = n;
+    fa.x = x;
+    fa.d = d;
+    fa.T = T;
+    fa.hashed = hashed ? 1 : 0;
+    fa.n_samples = n_samples;
+    fa.seed = seed;
+    fa.step = step;
+    fa.ht = at<uint16_t>(ws, W.ht);
+    fa.stride = W.stride;
+    fa.dz5 = at<uint16_t>(ws, W.dz) + dz_row(4) * W.stride;
+    fa.loss_part = at<float>(ws, W.loss_part);
+    const int64_t waves = n_pad / 32;
+    hipLaunchKernelGGL(k_mlp_forward<kModeTrain>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, fa);
+    BwdArgs ba{at<u32x4>(params, L.bwd), at<uint16_t>(ws, W.ht), at<uint16_t>(ws, W.dz), W.stride, n};
+    hipLaunchKernelGGL(k_mlp_backward, dim3(blocks_for(waves, 4)), dim3(256), 0, s, ba);
+    WgradArgs wa{};
+    wa.ht = at<uint16_t>(ws, W.ht);
+    wa.dz = at<uint16_t>(ws, W.dz);
+    wa.stride = W.stride;
+    wa.n_pad = n_pad;
+    wa.slice_len = kSliceLen;
+    wa.n_slices = (int)((n_pad + kSliceLen - 1) / kSliceLen);
+    wa.partial = at<float>(ws, W.partial);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(blocks_for((int64_t)kTiles * wa.n_slices, 4)), dim3(256), 0, s, wa);
+    hipLaunchKernelGGL(k_reduce_grad, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, wa.partial, wa.n_slices, grad,
+                       at<float>(ws, W.loss_part), waves, n, loss_out);
+    return check_launch("surrogate loss/gradient");
+}
+
+}  // namespace
+}  // namespace rv
 
 using namespace rv;
 
-extern "C" size_t rv_surrogate_bytes(void) { return 0; }
-extern "C" size_t rv_surrogate_train_workspace_bytes(int32_t) { return 0; }
-extern "C" size_t rv_surrogate_infer_workspace_bytes(int64_t) { return 0; }
-extern "C" rv_status rv_surrogate_init(void *, uint64_t, const float *, const float *, void *) {
-    set_error("rv_surrogate_init: not implemented");
-    return RV_ERR_UNSUPPORTED;
+extern "C" int64_t rv_surrogate_n_params(void) { return kNParams; }
+
+extern "C" size_t rv_surrogate_bytes(void) { return sur_layout().total; }
+
+extern "C" rv_status rv_surrogate_view(const void *params, rv_surrogate_arrays *out) {
+    clear_error();
+    RV_REQUIRE(params && out, RV_ERR_INVALID_ARG, "rv_surrogate_view: null pointer");
+    const SurLayout L = sur_layout();
+    void *p = const_cast<void *>(params);
+    out->header = at<float>(p, L.header);
+    out->master = at<float>(p, L.master);
+    out->adam_m = at<float>(p, L.m);
+    out->adam_v = at<float>(p, L.v);
+    out->packed = at<char>(p, L.fwd);
+    return RV_OK;
 }
-extern "C" rv_status rv_surrogate_train(void *, const float *, const float *, const float *, int64_t,
-                                        const rv_train_opts *, float *, void *, size_t, void *) {
-    set_error("rv_surrogate_train: not implemented");
-    return RV_ERR_UNSUPPORTED;
+
+extern "C" size_t rv_surrogate_train_workspace_bytes(int32_t batch) {
+    if (batch < 1) return 0;
+    return train_ws(batch).total;
 }
-extern "C" rv_status rv_surrogate_infer_xd(const void *, const float *, const float *, int64_t, float *, float *,
-                                           void *) {
-    set_error("rv_surrogate_infer_xd: not implemented");
-    return RV_ERR_UNSUPPORTED;
+
+extern "C" size_t rv_surrogate_infer_workspace_bytes(int64_t q_count) {
+    if (q_count < 0) return 0;
+    return align_up((size_t)q_count * sizeof(int64_t)) + kAlign;
 }
-extern "C" rv_status rv_surrogate_infer(const void *, const void *, const rv_gaussians *, const float *, int32_t,
-                                        const rv_trace_params *, int64_t, int64_t, float, float *, float *,
-                                        int64_t *, void *, size_t, void *) {
-    set_error("rv_surrogate_infer: not implemented");
-    return RV_ERR_UNSUPPORTED;
+
+extern "C" rv_status rv_surrogate_init(void *params, uint64_t seed, const float *box_lo_host, const float *box_hi_host,
+                                       const float *init_weights, void *stream) {
+    clear_error();
+    RV_REQUIRE(params && box_lo_host && box_hi_host, RV_ERR_INVALID_ARG, "rv_surrogate_init: null argument");
+    RV_REQUIRE(((uintptr_t)params % kAlign) == 0, RV_ERR_INVALID_ARG, "rv_surrogate_init: params not 256-byte aligned");
+    const SurLayout L = sur_layout();
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_set_header, dim3(1), dim3(64), 0, s, at<float>(params, L.header), box_lo_host[0],
+                       box_lo_host[1], box_lo_host[2], box_hi_host[0], box_hi_host[1], box_hi_host[2]);
+    if (init_weights)
+        hipLaunchKernelGGL(k_copy_f32, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, init_weights,
+                           at<float>(params, L.master), kNParams);
+    else
+        hipLaunchKernelGGL(k_init_hash, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, at<float>(params, L.master),
+                           seed);
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, at<float>(params, L.m), kNParams,
+                       0.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, at<float>(params, L.v), kNParams,
+                       0.0f);
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for(kFwdTotal + kBwdTotal, 256)), dim3(256), 0, s,
+                       at<float>(params, L.master), at<uint16_t>(params, L.fwd), at<uint16_t>(params, L.bwd));
+    return check_launch("rv_surrogate_init");
+}
+
+extern "C" rv_status rv_surrogate_loss_grad(const void *params, const float *x, const float *d, const float *T,
+                                            int64_t n, float *grad_out, float *loss_out, void *ws, size_t ws_bytes,
+                                            void *stream) {
+    clear_error();
+    RV_REQUIRE(params && x && d && T && grad_out && ws, RV_ERR_INVALID_ARG, "rv_surrogate_loss_grad: null argument");
+    RV_REQUIRE(n >= 1 && n <= (1LL << 30), RV_ERR_INVALID_ARG, "rv_surrogate_loss_grad: n out of range");
+    RV_REQUIRE(((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG, "rv_surrogate_loss_grad: ws not 256-byte aligned");
+    const TrainWs W = train_ws(n);
+    RV_REQUIRE(ws_bytes >= W.total, RV_ERR_WORKSPACE, "rv_surrogate_loss_grad: ws_bytes %zu < %zu", ws_bytes, W.total);
+    return loss_grad_impl(params, x, d, T, n, false, n, 0, 0, grad_out, loss_out, ws, W, (hipStream_t)stream);
+}
+
+extern "C" rv_status rv_surrogate_train(void *params, const float *x, const float *d, const float *T,
+                                        int64_t n_samples, const rv_train_opts *o, float *loss_log, void *ws,
+                                        size_t ws_bytes, void *stream) {
+    clear_error();
+    RV_REQUIRE(params && x && d && T && o && ws, RV_ERR_INVALID_ARG, "rv_surrogate_train: null argument");
+    RV_REQUIRE(n_samples >= 1, RV_ERR_INVALID_ARG, "rv_surrogate_train: n_samples < 1");
+    RV_REQUIRE(o->steps >= 0 && o->batch >= 128 && o->batch % 128 == 0, RV_ERR_INVALID_ARG,
+               "rv_surrogate_train: need steps >= 0 and batch a positive multiple of 128");
+    RV_REQUIRE(o->lr >= 0.f && o->beta1 >= 0.f && o->beta1 < 1.f && o->beta2 >= 0.f && o->beta2 < 1.f && o->eps > 0.f,
+               RV_ERR_INVALID_ARG, "rv_surrogate_train: bad optimiser settings");
+    RV_REQUIRE(((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG, "rv_surrogate_train: ws not 256-byte aligned");
+    const TrainWs W = train_ws(o->batch);
+    RV_REQUIRE(ws_bytes >= W.total, RV_ERR_WORKSPACE, "rv_surrogate_train: ws_bytes %zu < %zu", ws_bytes, W.total);
+    const SurLayout L = sur_layout();
+    hipStream_t s = (hipStream_t)stream;
+    float *grad = at<float>(ws, W.grad);
+    for (int64_t it = 0; it < o->steps; ++it) {
+        const int64_t gstep = o->step0 + it;
+        rv_status st = loss_grad_impl(params, x, d, T, o->batch, true, n_samples, o->seed, gstep, grad,
+                                      loss_log ? loss_log + it : nullptr, ws, W, s);
+        if (st != RV_OK) return st;
+        // cosine-decayed step size and bias corrections (host arithmetic, FP64)
+        double lr = o->lr;
+        if (o->total_steps > 0) {
+            double t = (double)std::min<int64_t>(std::max<int64_t>(gstep, 0), o->total_steps) / (double)o->total_steps;
+            lr = o->lr_min + 0.5 * (o->lr - o->lr_min) * (1.0 + std::cos(3.14159265358979323846 * t));
+        }
+        const double tt = (double)(gstep + 1);
+        const float c1 = (float)(1.0 - std::pow((double)o->beta1, tt));
+        const float c2 = (float)(1.0 - std::pow((double)o->beta2, tt));
+        hipLaunchKernelGGL(k_adam, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, at<float>(params, L.master),
+                           at<float>(params, L.m), at<float>(params, L.v), (const float *)grad, (float)lr, o->beta1,
+                           o->beta2, o->eps, c1, c2);
+        hipLaunchKernelGGL(k_pack, dim3(blocks_for(kFwdTotal + kBwdTotal, 256)), dim3(256), 0, s,
+                           at<float>(params, L.master), at<uint16_t>(params, L.fwd), at<uint16_t>(params, L.bwd));
+        st = check_launch("rv_surrogate_train");
+        if (st != RV_OK) return st;
+    }
+    return RV_OK;
+}
+
+extern "C" rv_status rv_surrogate_infer_xd(const void *params, const float *x, const float *d, int64_t n, float *vis,
+                                           float *unc, void *stream) {
+    clear_error();
+    RV_REQUIRE(params && vis && (n == 0 || (x && d)), RV_ERR_INVALID_ARG, "rv_surrogate_infer_xd: null argument");
+    RV_REQUIRE(n >= 0, RV_ERR_INVALID_ARG, "rv_surrogate_infer_xd: n < 0");
+    if (n == 0) return RV_OK;
+    const SurLayout L = sur_layout();
+    FwdArgs fa{};
+    fa.master = at<float>(params, L.master);
+    fa.fwd = at<u32x4>(params, L.fwd);
+    fa.header = at<float>(params, L.header);
+    fa.n = n;
+    fa.x = x;
+    fa.d = d;
+    fa.vis = vis;
+    fa.unc = unc;
+    hipLaunchKernelGGL(k_mlp_forward<kModeXd>, dim3(blocks_for((n + 31) / 32, 4)), dim3(256), 0, (hipStream_t)stream,
+                       fa);
+    return check_launch("rv_surrogate_infer_xd");
+}
+
+extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, const rv_gaussians *g, const float *dirs,
+                                        int32_t K, const rv_trace_params *p, int64_t q_begin, int64_t q_count,
+                                        float tau, float *vis, float *unc, int64_t *n_fallback, void *ws,
+                                        size_t ws_bytes, void *stream) {
+    clear_error();
+    RV_REQUIRE(params && g && dirs && p && vis, RV_ERR_INVALID_ARG, "rv_surrogate_infer: null argument");
+    RV_REQUIRE(g->mean && g->log_scale && g->n >= 1 && K >= 1, RV_ERR_INVALID_ARG, "rv_surrogate_infer: bad scene");
+    RV_REQUIRE(p->dir_mode == 0 || (p->dir_mode == 1 && g->normal), RV_ERR_INVALID_ARG,
+               "rv_surrogate_infer: bad dir_mode or missing normals");
+    RV_REQUIRE(p->sigma_cut > 0.0f && p->sigma_cut <= kBuildSigma && p->alpha_min > 0.0f && p->alpha_max < 1.0f &&
+                   p->T_min >= 0.0f && p->T_min < 1.0f,
+               RV_ERR_INVALID_ARG, "rv_surrogate_infer: bad trace parameters");
+    RV_REQUIRE(q_begin >= 0 && q_count >= 0 && q_begin + q_count <= g->n * (int64_t)K, RV_ERR_INVALID_ARG,
+               "rv_surrogate_infer: query range outside [0, n*K)");
+    if (q_count == 0) return RV_OK;
+    RV_REQUIRE(ws && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG, "rv_surrogate_infer: ws missing or unaligned");
+    RV_REQUIRE(ws_bytes >= rv_surrogate_infer_workspace_bytes(q_count), RV_ERR_WORKSPACE,
+               "rv_surrogate_infer: ws_bytes %zu < %zu", ws_bytes, rv_surrogate_infer_workspace_bytes(q_count));
+    const SurLayout L = sur_layout();
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *count = at<unsigned long long>(ws, 0);
+    int64_t *list = at<int64_t>(ws, kAlign);
+    hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(256), 0, s, reinterpret_cast<float *>(count), (int64_t)2, 0.0f);
+    FwdArgs fa{};
+    fa.master = at<float>(params, L.master);
+    fa.fwd = at<u32x4>(params, L.fwd);
+    fa.header = at<float>(params, L.header);
+    fa.n = q_count;
+    fa.vis = vis;
+    fa.unc = unc;
+    fa.gmean = g->mean;
+    fa.gnormal = p->dir_mode ? g->normal : nullptr;
+    fa.dirs = dirs;
+    fa.K = K;
+    fa.dir_mode = p->dir_mode;
+    fa.q_begin = q_begin;
+    fa.tau = tau;
+    fa.fb_list = bvh ? list : nullptr;
+    fa.fb_count = count;
+    hipLaunchKernelGGL(k_mlp_forward<kModeGrid>, dim3(blocks_for((q_count + 31) / 32, 4)), dim3(256), 0, s, fa);
+    if (bvh) {
+        const BvhLayout BL = bvh_layout(g->n);
+        const Cuts c = make_cuts(*p);
+        hipLaunchKernelGGL(k_fallback_trace, dim3(256 * 8), dim3(256), 0, s, at<float4>(bvh, BL.nodes),
+                           at<float4>(bvh, BL.leaf_rec), g->mean, p->dir_mode ? g->normal : nullptr, g->log_scale, g->n,
+                           dirs, K, c, q_begin, (const int64_t *)list, (const unsigned long long *)count, vis,
+                           n_fallback);
+    } else if (n_fallback) {
+        hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(n_fallback), (int64_t)2,
+                           0.0f);
+    }
+    return check_launch("rv_surrogate_infer");
+}
+
+extern "C" rv_status rv_ray_setup(const rv_gaussians *g, const float *dirs, int32_t K, const rv_trace_params *p,
+                                  const int64_t *ray_ids, int64_t n, float *out_o, float *out_d, void *stream) {
+    clear_error();
+    RV_REQUIRE(g && dirs && p && g->mean, RV_ERR_INVALID_ARG, "rv_ray_setup: null argument");
+    RV_REQUIRE(g->n >= 1 && K >= 1 && n >= 0, RV_ERR_INVALID_ARG, "rv_ray_setup: bad sizes");
+    RV_REQUIRE(p->dir_mode == 0 || (p->dir_mode == 1 && g->normal), RV_ERR_INVALID_ARG,
+               "rv_ray_setup: bad dir_mode or missing normals");
+    if (n == 0) return RV_OK;
+    RV_REQUIRE(ray_ids && out_o && out_d, RV_ERR_INVALID_ARG, "rv_ray_setup: null ids or outputs");
+    hipLaunchKernelGGL(k_ray_setup, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, g->mean,
+                       p->dir_mode ? g->normal : nullptr, g->n, dirs, K, p->dir_mode, ray_ids, n, out_o, out_d);
+    return check_launch("rv_ray_setup");
 }
