@@ -58,7 +58,84 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy probe (known-size reference for counters)")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--sur-train-samples", type=int, default=8_000_000)
+    ap.add_argument("--sur-steps", type=int, default=2000)
+    ap.add_argument("--sur-batch", type=int, default=16384)
+    ap.add_argument("--sur-mae", type=float, default=0.02, help="target mean absolute visibility error")
     return ap.parse_args()
+
+
+MLP_FLOPS_PER_QUERY = 2 * (64 * 256 + 3 * 256 * 256 + 256 * 2)   # dense layers, padded input width 64
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, plain_rays_per_s):
+    """Train the MLP surrogate on the tracer's samples, pick the fallback
+    threshold on held-out rays, then time the surrogate path over every query."""
+    from paper_2311_16043_amd import Surrogate, ray_setup
+    dev = vis_ray.device
+    n, K = vis_ray.shape
+    R = n * K
+    T_all = vis_ray.reshape(-1)
+    gen = torch.Generator(device="cpu").manual_seed(2311)
+    perm = torch.randperm(R, generator=gen)
+    tr_ids = perm[: args.sur_train_samples].to(dev)
+    ho_ids = perm[-1_000_000:].to(dev)
+    o, d = ray_setup(g, dirs, tr_ids, prm)
+    T_tr = T_all[tr_ids]
+    lo = g.mean.min(0).values.cpu().tolist()
+    hi = g.mean.max(0).values.cpu().tolist()
+    net = Surrogate(lo, hi, seed=1, device=dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    log = net.train(o, d, T_tr, steps=args.sur_steps, batch=args.sur_batch, lr=2e-3, lr_min=5e-5, seed=7)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    del o, d, T_tr
+    # threshold: rank held-out queries by predicted error, trace the top fraction
+    oh, dh = ray_setup(g, dirs, ho_ids, prm)
+    vh, uh = net.infer_xd(oh, dh)
+    err = (vh - T_all[ho_ids]).abs()
+    order = torch.argsort(uh, descending=True)
+    e_sorted = err[order]
+    kept_err = torch.flip(torch.cumsum(torch.flip(e_sorted, [0]), 0), [0]) / err.numel()  # MAE if the first j are traced
+    # a 5 % margin so that the error over all queries stays within the target
+    ok = torch.nonzero(kept_err <= 0.95 * args.sur_mae)
+    j = int(ok[0]) if ok.numel() else err.numel()
+    tau = float(uh[order[j]]) if j < err.numel() else float("-inf")
+    # timed: surrogate with fallback over all R queries, and the network alone
+    out_v = torch.empty(R, dtype=torch.float32, device=dev)
+    out_u = torch.empty(R, dtype=torch.float32, device=dev)
+    ws = torch.empty(int(__import__("paper_2311_16043_amd")._lib.load().rv_surrogate_infer_workspace_bytes(R)),
+                     dtype=torch.uint8, device=dev)
+
+    def sweep(tau_, with_bvh):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, _, nfb = net.infer_grid(g, dirs, prm, 0, R, tau=tau_, bvh=bvh if with_bvh else None, out_vis=out_v,
+                                   out_unc=out_u, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1000.0, int(nfb.item())
+
+    sweep(float("inf"), False)
+    mlp_s, _ = sweep(float("inf"), False)
+    mae_net = float((out_v - T_all).abs().mean())
+    fb_s, nfb = sweep(tau, True)
+    mae = float((out_v - T_all).abs().mean())
+    q_per_s = R / fb_s
+    return dict(
+        queries=R, train_samples=int(tr_ids.numel()), train_steps=args.sur_steps, batch=args.sur_batch,
+        train_s=train_s, train_samples_per_s=args.sur_steps * args.sur_batch / train_s,
+        loss_first=float(log[0]), loss_last=float(log[-1]),
+        tau=tau, target_mae=args.sur_mae, fallback_fraction=nfb / R, mae=mae,
+        queries_per_s=q_per_s, speedup_vs_plain=q_per_s / plain_rays_per_s,
+        network_only=dict(queries_per_s=R / mlp_s, mae=mae_net, ms=mlp_s * 1000.0,
+                          tflops=MLP_FLOPS_PER_QUERY * R / mlp_s / 1e12,
+                          mfma_frac=MLP_FLOPS_PER_QUERY * R / mlp_s / 1e12 / BF16_PEAK_TFLOPS),
+        ms=fb_s * 1000.0,
+    )
 
 
 def copy_probe(torch, nbytes=1 << 31, iters=5):
@@ -206,6 +283,9 @@ def main():
             "hits_per_ray": st["hits"] / rays,
         },
     }
+    if not args.no_surrogate and name != "tiny":
+        out["surrogate"] = surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, rays / trace_s)
+        print(f"[bench] surrogate: {json.dumps(out['surrogate'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, dirs_np, dir_mode, args.cpu_seconds)
     print(json.dumps(out), flush=True)
