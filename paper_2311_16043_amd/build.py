@@ -32,6 +32,10 @@ COMMON_FLAGS = [
     "-fhip-fp32-correctly-rounded-divide-sqrt",
     # hardware float atomics on coarse-grained device memory
     "-munsafe-fp-atomics",
+    # fuse multiply-adds only within one expression, never across statements:
+    # the same source then rounds the same way in every kernel it is inlined into
+    # (the ray-list and all-ray traversals give identical bits)
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
     "-I", INCLUDE,
     "-I", CSRC,

@@ -127,6 +127,208 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_chunks(const float4 *__re
     }
 }
 
+// ---- pooled traversal -----------------------------------------------------------
+//
+// A wave owns a pool of rays: 64 Gaussians adjacent in sorted order times a
+// chunk of kPoolS consecutive directions. Lanes that have no ray take the next
+// pool rays (ballot + popcount). Each iteration, lanes with traversal work and
+// room in their leaf FIFO visit one node, appending hit leaves instead of
+// testing them; the leaf test then runs as one block for all lanes with a
+// pending leaf once enough of them have one, so the expensive exact test
+// executes with most lanes active instead of inside every node step. Leaves
+// are tested in discovery (FIFO) order, so each ray's product, and its early
+// exit, is the same as a single-ray traversal's, bit for bit.
+constexpr int kPoolS = 8;
+constexpr int kFifo = 8;
+constexpr int kPoolRing = 8;
+constexpr int kLeafMin = 32;
+
+struct PoolMap {
+    int64_t n;
+    int K, n_chunks;
+    int64_t n_items;   // ceil(n / 64) * n_chunks
+    int64_t n_blocks;
+};
+
+inline PoolMap make_pool(int64_t n, int K) {
+    PoolMap pm;
+    pm.n = n;
+    pm.K = K;
+    pm.n_chunks = (K + kPoolS - 1) / kPoolS;
+    pm.n_items = ((n + 63) / 64) * (int64_t)pm.n_chunks;
+    pm.n_blocks = (pm.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
+    return pm;
+}
+
+template <bool kCount>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__restrict__ nodes,
+                                                            const float4 *__restrict__ rec,
+                                                            const float4 *__restrict__ origins,
+                                                            const float *__restrict__ dirs, PoolMap pm, Cuts c,
+                                                            float *__restrict__ vis_ray, double *__restrict__ partial,
+                                                            unsigned long long *__restrict__ totals) {
+    __shared__ int32_t stk[kPoolRing * kTraceBlock];
+    __shared__ int32_t fifo[kFifo * kTraceBlock];
+    __shared__ float tbuf[kWavesPerBlock][kPoolS * 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+    if (w >= pm.n_items) return;  // wave-uniform
+    const int64_t grp = w / pm.n_chunks;
+    const int chunk = (int)(w - grp * pm.n_chunks);
+    const int64_t m0 = grp * 64;
+    const int nv = (int)min<int64_t>(64, pm.n - m0);
+    const int k0 = chunk * kPoolS;
+    const int s_eff = min(kPoolS, pm.K - k0);
+    const int pool_n = nv * s_eff;
+    const uint64_t lt = (1ull << lane) - 1ull;
+
+    // this lane's ray
+    RingStack<kPoolRing> st;
+    int32_t spill[RingStack<kPoolRing>::kSpill];
+    st.lds = stk + threadIdx.x;
+    st.spill = spill;
+    st.stride = kTraceBlock;
+    st.sp = 0;
+    int32_t *my_fifo = fifo + threadIdx.x;
+    int fhead = 0, fcount = 0;
+    bool has = false;
+    int slot = 0;  // pool index of the current ray
+    f3 o = mk(0.f, 0.f, 0.f), d = o, inv = o;
+    float tmin = 0.f, T = 1.f;
+    int32_t self = -1, self_leaf = -1, node = -1;
+    int64_t budget = 0;
+    int64_t cn = 0, cl = 0, ch = 0;
+    NoHit none;
+    int next = 0;  // wave-uniform
+
+    while (true) {
+        // refill idle lanes from the pool
+        const uint64_t need = __ballot(!has);
+        if (need != 0 && next < pool_n) {
+            const int idx = next + __popcll(need & lt);
+            if (!has && idx < pool_n) {
+                const int oi = idx % nv, j = idx / nv;
+                const int64_t m = m0 + oi;
+                const float4 r0 = rec[4 * m];
+                const float4 og = origins[m];
+                const f3 nrm = mk(og.x, og.y, og.z);
+                f3 b1, b2;
+                onb_duff(nrm, b1, b2);
+                o = mk(r0.x, r0.y, r0.z);
+                d = ray_direction(dirs, k0 + j, c.dir_mode, nrm, b1, b2);
+                inv = safe_inv(d);
+                tmin = c.tmin_scale * og.w;
+                self = __float_as_int(rec[4 * m + 1].w);
+                self_leaf = (int32_t)m;
+                T = 1.0f;
+                st.sp = 0;
+                fhead = 0;
+                fcount = 0;
+                node = pm.n > 1 ? 0 : -1;
+                budget = pm.n;
+                slot = idx;
+                has = true;
+            }
+            next += __popcll(need);
+        }
+        if (__ballot(has) == 0) break;
+
+        // node phase: one internal node per lane with traversal work and FIFO room
+        const bool can_node = has && node >= 0 && fcount <= kFifo - 2;
+        if (can_node) {
+            if (--budget < 0) {
+                node = -1;
+                fcount = 0;
+                T = __int_as_float(0x7fc00000);
+            } else {
+                const float4 a = nodes[4 * node + 0];
+                const float4 b = nodes[4 * node + 1];
+                const float4 cc = nodes[4 * node + 2];
+                const float4 ids = nodes[4 * node + 3];
+                const int32_t left = __float_as_int(ids.x), right = __float_as_int(ids.y);
+                const bool hl = slab_hit(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, tmin);
+                const bool hr = slab_hit(b.z, b.w, cc.x, cc.y, cc.z, cc.w, o, inv, tmin);
+                if (kCount) ++cn;
+                if (hl && left < 0) {
+                    my_fifo[((fhead + fcount) & (kFifo - 1)) * kTraceBlock] = ~left;
+                    ++fcount;
+                }
+                if (hr && right < 0) {
+                    my_fifo[((fhead + fcount) & (kFifo - 1)) * kTraceBlock] = ~right;
+                    ++fcount;
+                }
+                const bool gl = hl && left >= 0, gr = hr && right >= 0;
+                if (gl && gr) {
+                    if (st.full()) {
+                        node = -1;
+                        fcount = 0;
+                        T = __int_as_float(0x7fc00000);
+                    } else {
+                        st.push(right);
+                        node = left;
+                    }
+                } else if (gl) {
+                    node = left;
+                } else if (gr) {
+                    node = right;
+                } else if (!st.empty()) {
+                    node = st.pop();
+                } else {
+                    node = -1;
+                }
+            }
+        }
+
+        // leaf phase: test one pending leaf per lane when enough lanes have one,
+        // when a lane cannot traverse for lack of FIFO room, or when no lane can traverse
+        const uint64_t pend = __ballot(has && fcount > 0);
+        const uint64_t blocked = __ballot(has && fcount > kFifo - 2);
+        const uint64_t trav = __ballot(has && node >= 0 && fcount <= kFifo - 2);
+        if (pend != 0 && (__popcll(pend) >= kLeafMin || blocked != 0 || trav == 0)) {
+            if (has && fcount > 0) {
+                const int32_t leaf = my_fifo[fhead * kTraceBlock];
+                fhead = (fhead + 1) & (kFifo - 1);
+                --fcount;
+                const float f = leaf_factor(rec, leaf, o, d, tmin, self, self_leaf, c, none, T);
+                if (kCount) {
+                    ++cl;
+                    ch += (f != 1.0f);
+                }
+                T *= f;
+                if (T < c.T_stop) {
+                    node = -1;
+                    fcount = 0;
+                }
+            }
+        }
+
+        // finished rays park their T in the wave's pool buffer
+        if (has && node < 0 && fcount == 0) {
+            tbuf[wv][slot] = T;
+            has = false;
+        }
+    }
+    // every lane has left the loop: the pool buffer is complete
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nv) {
+        const int64_t m = m0 + lane;
+        const int32_t src = __float_as_int(rec[4 * m + 1].w);
+        double sum = 0.0;
+        for (int j = 0; j < s_eff; ++j) {
+            const float t = tbuf[wv][j * nv + lane];
+            if (vis_ray) vis_ray[(int64_t)src * pm.K + k0 + j] = t;
+            sum += (double)t;
+        }
+        if (partial) partial[(int64_t)chunk * pm.n + src] = sum;
+    }
+    if (kCount) {
+        atomicAdd(totals + 0, (unsigned long long)cn);
+        atomicAdd(totals + 1, (unsigned long long)cl);
+        atomicAdd(totals + 2, (unsigned long long)ch);
+    }
+}
+
 // vis_mean[i] = (sum over chunks, in chunk order, of the FP64 partials) / K.
 __global__ __launch_bounds__(256) void k_mean_from_partials(const double *__restrict__ partial, int64_t n,
                                                             int n_chunks, int K, float *__restrict__ vis_mean) {
@@ -300,8 +502,8 @@ using namespace rv;
 
 extern "C" size_t rv_trace_workspace_bytes(int64_t n, int32_t K) {
     if (n < 1 || K < 1) return kAlign;
-    const ChunkMap cm = make_chunks(n, K);
-    return align_up((size_t)cm.n_chunks * (size_t)n * sizeof(double)) + kAlign;
+    const PoolMap pm = make_pool(n, K);
+    return align_up((size_t)pm.n_chunks * (size_t)n * sizeof(double)) + kAlign;
 }
 
 extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
@@ -311,7 +513,7 @@ extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g,
     rv_status st = validate_trace("rv_trace_visibility", bvh, g, dirs, K, p);
     if (st != RV_OK) return st;
     RV_REQUIRE(vis_ray || vis_mean, RV_ERR_INVALID_ARG, "rv_trace_visibility: both outputs are NULL");
-    const ChunkMap cm = make_chunks(g->n, K);
+    const PoolMap pm = make_pool(g->n, K);
     double *partial = nullptr;
     if (vis_mean) {
         RV_REQUIRE(ws && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG,
@@ -323,12 +525,12 @@ extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g,
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_trace_chunks<false>, dim3((unsigned)cm.n_blocks), dim3(kTraceBlock), 0, s,
-                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, cm, c,
+    hipLaunchKernelGGL(k_trace_pool<false>, dim3((unsigned)pm.n_blocks), dim3(kTraceBlock), 0, s,
+                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, pm, c,
                        vis_ray, partial, (unsigned long long *)nullptr);
     if (vis_mean)
         hipLaunchKernelGGL(k_mean_from_partials, dim3(grid_for(g->n, 256)), dim3(256), 0, s, partial, g->n,
-                           cm.n_chunks, K, vis_mean);
+                           pm.n_chunks, K, vis_mean);
     return check_launch("rv_trace_visibility");
 }
 
@@ -341,14 +543,14 @@ extern "C" rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, cons
     RV_REQUIRE(totals, RV_ERR_INVALID_ARG, "rv_trace_stats: null totals");
     (void)ws;
     (void)ws_bytes;
-    const ChunkMap cm = make_chunks(g->n, K);
+    const PoolMap pm = make_pool(g->n, K);
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(totals), (int64_t)6,
                        0u);
-    hipLaunchKernelGGL(k_trace_chunks<true>, dim3((unsigned)cm.n_blocks), dim3(kTraceBlock), 0, s,
-                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, cm, c,
+    hipLaunchKernelGGL(k_trace_pool<true>, dim3((unsigned)pm.n_blocks), dim3(kTraceBlock), 0, s,
+                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, pm, c,
                        (float *)nullptr, (double *)nullptr, (unsigned long long *)totals);
     return check_launch("rv_trace_stats");
 }

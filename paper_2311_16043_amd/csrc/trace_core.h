@@ -218,19 +218,24 @@ struct RayState {
         const bool hl = slab_hit(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, tmin);
         const bool hr = slab_hit(b.z, b.w, cc.x, cc.y, cc.z, cc.w, o, inv, tmin);
         if (kCount) ++*n_nodes;
+        // leaves in discovery order, the exit checked after each (T < T_min)
         if (hl && left < 0) {
             const float f = leaf_factor(rec, ~left, o, d, tmin, self, self_leaf, c, on_hit, T);
             if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
             T *= f;
+            if (T < c.T_stop) {
+                node = -1;
+                return true;
+            }
         }
         if (hr && right < 0) {
             const float f = leaf_factor(rec, ~right, o, d, tmin, self, self_leaf, c, on_hit, T);
             if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
             T *= f;
-        }
-        if (T < c.T_stop) {
-            node = -1;
-            return true;
+            if (T < c.T_stop) {
+                node = -1;
+                return true;
+            }
         }
         const bool gl = hl && left >= 0, gr = hr && right >= 0;
         if (gl && gr) {
