@@ -236,9 +236,11 @@ def main():
     ms_per_step = 1000.0 * wall / args.steps
     value = rays * args.steps / wall
 
-    # algorithmic bytes of the traversal kernel (deterministic for this BVH)
+    # algorithmic bytes of the traversal kernel (deterministic for this BVH):
+    # origin data, one 128-byte four-wide record per node visit, one 64-byte
+    # record per leaf test, the ray's output, and the mean per Gaussian
     st = trace_stats(bvh, g, dirs, prm)
-    alg_bytes = 24 * rays + 64 * st["nodes"] + 64 * st["leaves"] + 4 * rays + 4 * n
+    alg_bytes = 24 * rays + 128 * st["nodes"] + 64 * st["leaves"] + 4 * rays + 4 * n
     trace_s = float(np.mean(trace_ms)) / 1000.0
     achieved = alg_bytes / trace_s / 1e9
     print(f"[bench] step {ms_per_step:.2f} ms (build {np.mean(build_ms):.3f} ms, trace {np.mean(trace_ms):.3f} ms); "
@@ -281,6 +283,9 @@ def main():
             "nodes_per_ray": st["nodes"] / rays,
             "leaves_per_ray": st["leaves"] / rays,
             "hits_per_ray": st["hits"] / rays,
+            # brute force reads every other Gaussian's 64-byte record per ray
+            "brute_force_bytes_per_ray": 64 * (n - 1),
+            "work_avoided": 64 * (n - 1) * rays / alg_bytes,
         },
     }
     if not args.no_surrogate and name != "tiny":

@@ -99,6 +99,7 @@ typedef struct rv_bvh_arrays {
     const float *leaf_records;  /* [n][16] per sorted leaf: mu[3], o, W row0[3], src, W row1[3], pad, W row2[3], pad */
     const float *leaf_boxes;    /* [n][6]  per sorted leaf: lo[3], hi[3] (3-sigma box, widened outward) */
     const float *origins;       /* [n][4]  per sorted leaf: unit normal[3], t_min */
+    const float *nodes4;        /* [n-1][32] four-wide node per internal node, see rv_build_bvh */
 } rv_bvh_arrays;
 
 /* const char* describing the last failure on the calling thread ("" if none). */
@@ -128,7 +129,12 @@ size_t rv_build_workspace_bytes(int64_t n);
  * internal id, or ~m for leaf m); per-leaf records in sorted order; bottom-up
  * refit of the 3-sigma boxes. Node record (16 floats): left-child box lo[3],
  * hi[3], right-child box lo[3], hi[3], then the left and right child ids as
- * int32 bit patterns, then 2 unused words.
+ * int32 bit patterns, then 2 unused words. Four-wide record of internal
+ * node i (32 floats, the one the tracer walks): the children of i's two
+ * children, with a leaf child kept in its own slot and the next slot empty
+ * (id INT32_MIN): lo_x[4], lo_y[4], lo_z[4], hi_x[4], hi_y[4], hi_z[4],
+ * child ids[4] as int32 bit patterns, 4 unused words; boxes copied bit for
+ * bit from the binary records.
  * The result depends only on the inputs (bit-identical across runs).
  * Errors: RV_ERR_INVALID_ARG (null pointers, n < 1, n > RV_MAX_GAUSSIANS,
  * unaligned bvh), RV_ERR_WORKSPACE (bvh_bytes or ws_bytes too small),

@@ -33,7 +33,7 @@ class RvTraceParams(C.Structure):
 class RvBvhArrays(C.Structure):
     _fields_ = [("n", C.c_int64), ("header", C.c_void_p), ("keys", C.c_void_p), ("perm", C.c_void_p),
                 ("nodes", C.c_void_p), ("parent", C.c_void_p), ("leaf_records", C.c_void_p),
-                ("leaf_boxes", C.c_void_p), ("origins", C.c_void_p)]
+                ("leaf_boxes", C.c_void_p), ("origins", C.c_void_p), ("nodes4", C.c_void_p)]
 
 
 class RvTrainOpts(C.Structure):

@@ -363,6 +363,113 @@ __global__ __launch_bounds__(256) void k_refit(int64_t n, const float *__restric
     }
 }
 
+// ---- four-wide nodes ----------------------------------------------------------
+
+// Compressed wide record of internal node i: the children of i's two
+// children (a child that is a leaf keeps its own slot, the next slot is
+// empty), so one traversal step tests up to four boxes from three 16-byte
+// loads. Every internal node gets a record; a traversal from the root only
+// lands on nodes an even number of binary levels down. Layout (12 words in a
+// 64-byte slot):
+//   words 0-2   origin O (float), at or below the lowest child plane
+//   word 3      bytes 0-2: per-axis step exponents, step_a = 2^(byte - 127);
+//               byte 3: kind of slot j in bits 2j..2j+1 (0 empty, 1 internal
+//               node, 2 leaf)
+//   words 4-9   lo_x, lo_y, lo_z, hi_x, hi_y, hi_z planes, one byte per slot
+//               (byte j = slot j): plane = O_a + q step_a
+//   words 10-11 index of slot 2s for side s; slot 2s + 1 holds that index + 1
+//               (a node's two children always have consecutive indices)
+// Planes are rounded outward from the refitted binary boxes after widening
+// them by eta = (largest root-box coordinate + root diagonal + 1) 2^-20, in
+// exact (double) arithmetic, so a traversal that evaluates the plane
+// distances as fma(q, step/d, (O - o)/d) (error far below eta) never rejects
+// a box the exact ray enters.
+__global__ __launch_bounds__(256) void k_collapse4(int64_t n, const float *__restrict__ nodes,
+                                                   const float *__restrict__ header, float *__restrict__ nodes4) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    double ext = 0.0, diag2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double l = header[6 + a], h = header[9 + a];
+        ext = fmax(ext, fmax(fabs(l), fabs(h)));
+        diag2 += (h - l) * (h - l);
+    }
+    const double eta = (ext + sqrt(diag2) + 1.0) * 0x1p-20;
+    const float *r = nodes + 16 * i;
+    float box[4][6];
+    uint32_t kind[4];
+    int32_t base[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int32_t c = __float_as_int(r[12 + side]);
+        const int s0 = 2 * side, s1 = 2 * side + 1;
+        if (c < 0) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                box[s0][a] = r[6 * side + a];
+                box[s1][a] = r[6 * side + a];  // unused; keeps the node box unchanged
+            }
+            kind[s0] = 2u;
+            kind[s1] = 0u;
+            base[side] = ~c;
+        } else {
+            const float *rc = nodes + 16 * (int64_t)c;
+            const int32_t lc = __float_as_int(rc[12]), rcid = __float_as_int(rc[13]);
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                box[s0][a] = rc[a];
+                box[s1][a] = rc[6 + a];
+            }
+            kind[s0] = lc < 0 ? 2u : 1u;
+            kind[s1] = rcid < 0 ? 2u : 1u;
+            base[side] = lc < 0 ? ~lc : lc;
+        }
+    }
+    uint32_t words[12];
+    uint32_t meta = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double lo = box[0][a], hi = box[0][3 + a];
+#pragma unroll
+        for (int j = 1; j < 4; ++j) {
+            lo = fmin(lo, (double)box[j][a]);
+            hi = fmax(hi, (double)box[j][3 + a]);
+        }
+        // origin: a float at or below lo - eta
+        const double od = lo - eta;
+        float O = (float)od;
+        if ((double)O > od) O = nextafterf(O, -__builtin_inff());
+        // smallest power-of-two step with 255 steps reaching hi + eta
+        int e;
+        frexp((hi + eta - (double)O) / 255.0, &e);
+        e = max(-126, min(127, e));
+        const double step = ldexp(1.0, e);
+        uint32_t qlo = 0, qhi = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double fl = floor(((double)box[j][a] - eta - (double)O) / step);
+            const double fh = ceil(((double)box[j][3 + a] + eta - (double)O) / step);
+            qlo |= (uint32_t)fmin(fmax(fl, 0.0), 255.0) << (8 * j);
+            qhi |= (uint32_t)fmin(fmax(fh, 0.0), 255.0) << (8 * j);
+        }
+        words[a] = __float_as_uint(O);
+        words[4 + a] = qlo;
+        words[7 + a] = qhi;
+        meta |= (uint32_t)(e + 127) << (8 * a);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) meta |= kind[j] << (24 + 2 * j);
+    words[3] = meta;
+    words[10] = (uint32_t)base[0];
+    words[11] = (uint32_t)base[1];
+    uint4 *dst = reinterpret_cast<uint4 *>(nodes4) + 4 * i;
+    dst[0] = make_uint4(words[0], words[1], words[2], words[3]);
+    dst[1] = make_uint4(words[4], words[5], words[6], words[7]);
+    dst[2] = make_uint4(words[8], words[9], words[10], words[11]);
+    dst[3] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
@@ -389,6 +496,7 @@ extern "C" rv_status rv_bvh_view(const void *bvh, int64_t n, rv_bvh_arrays *out)
     out->leaf_records = at<float>(bvh, L.leaf_rec);
     out->leaf_boxes = at<float>(bvh, L.leaf_box);
     out->origins = at<float>(bvh, L.origins);
+    out->nodes4 = at<float>(bvh, L.nodes4);
     return RV_OK;
 }
 
@@ -453,6 +561,8 @@ extern "C" rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
                            reinterpret_cast<float4 *>(nodes), parent);
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, flags, n - 1, 0u);
         hipLaunchKernelGGL(k_refit, dim3(grid_for(n, 256)), dim3(256), 0, s, n, box, parent, nodes, flags, header);
+        hipLaunchKernelGGL(k_collapse4, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, n, nodes, header,
+                           at<float>(bvh, L.nodes4));
     } else {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(parent), (int64_t)1,
                            0xffffffffu);

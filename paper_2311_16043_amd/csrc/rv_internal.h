@@ -41,8 +41,14 @@ constexpr float kBuildSigma = 3.0f;
 // Header floats: lo[3], hi[3] of the means; root box lo[3], hi[3]; n (as float bits) ...
 constexpr int kHeaderFloats = 16;
 
+// Child id of an unused or missed slot of a four-wide node as the traversal
+// reports it (leaves are ~m, internal nodes their binary id >= 0).
+constexpr int32_t kEmptyChild = INT32_MIN;
+// Bytes per compressed four-wide node (48 used).
+constexpr size_t kNode4Bytes = 64;
+
 struct BvhLayout {
-    size_t header, keys, perm, nodes, parent, leaf_rec, leaf_box, origins, total;
+    size_t header, keys, perm, nodes, parent, leaf_rec, leaf_box, origins, nodes4, total;
 };
 
 inline BvhLayout bvh_layout(int64_t n) {
@@ -57,6 +63,7 @@ inline BvhLayout bvh_layout(int64_t n) {
     L.leaf_rec = off; off = align_up(off + nn * 64);
     L.leaf_box = off; off = align_up(off + nn * 24);
     L.origins = off; off = align_up(off + nn * 16);
+    L.nodes4 = off; off = align_up(off + (nn > 1 ? nn - 1 : 1) * kNode4Bytes);
     L.total = off;
     return L;
 }

@@ -586,7 +586,7 @@ __global__ __launch_bounds__(64) void k_set_header(float *__restrict__ h, float 
 constexpr int kFbRing = 16;
 
 // Persistent grid-stride loop over the compacted fallback list.
-__global__ __launch_bounds__(256) void k_fallback_trace(const float4 *__restrict__ nodes, const float4 *__restrict__ rec,
+__global__ __launch_bounds__(256) void k_fallback_trace(const float4 *__restrict__ nodes4, const float4 *__restrict__ rec,
                                                         const float *__restrict__ mean, const float *__restrict__ normal,
                                                         const float *__restrict__ log_scale, int64_t n,
                                                         const float *__restrict__ dirs, int K, Cuts c, int64_t q_begin,
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(256) void k_fallback_trace(const float4 *__restrict
         NoHit none;
         rs.start(mk(mean[3 * i], mean[3 * i + 1], mean[3 * i + 2]), ray_direction(dirs, k, c.dir_mode, nrm, b1, b2),
                  c.tmin_scale * smax, (int32_t)i, -1, n);
-        while (rs.node >= 0 && !rs.step(nodes, rec, c, none)) {
+        while (rs.node >= 0 && !rs.step(nodes4, rec, c, none)) {
         }
         vis[s] = rs.T;
     }
@@ -895,7 +895,7 @@ extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, con
     if (bvh) {
         const BvhLayout BL = bvh_layout(g->n);
         const Cuts c = make_cuts(*p);
-        hipLaunchKernelGGL(k_fallback_trace, dim3(256 * 8), dim3(256), 0, s, at<float4>(bvh, BL.nodes),
+        hipLaunchKernelGGL(k_fallback_trace, dim3(256 * 8), dim3(256), 0, s, at<float4>(bvh, BL.nodes4),
                            at<float4>(bvh, BL.leaf_rec), g->mean, p->dir_mode ? g->normal : nullptr, g->log_scale, g->n,
                            dirs, K, c, q_begin, (const int64_t *)list, (const unsigned long long *)count, vis,
                            n_fallback);

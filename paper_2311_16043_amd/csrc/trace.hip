@@ -3,16 +3,16 @@
 // per-Gaussian average over the K directions (the "averaged visibility" of the
 // ablation study, Sec. 5.4).
 //
-// Work mapping. A wave takes 64 Gaussians adjacent in Morton (sorted-leaf)
-// order and one chunk of S consecutive directions; each lane traces its
-// Gaussian's S rays, one BVH node per loop iteration, and starts its next ray
-// as soon as the current one ends (lanes never wait on each other's rays).
-// Chunking gives ~16M lanes, so the hardware dispatcher balances the skewed
-// per-ray work across many waves instead of waiting on the slowest Gaussian.
-// Blocks are renumbered so that each XCD (round-robin dispatch) walks a
-// contiguous range of the Morton order and its L2 sees a compact part of the
-// tree. Each lane writes one FP64 partial sum; a second kernel adds a
-// Gaussian's partials in chunk order (deterministic, no atomics).
+// Work mapping. The forward kernel gives each wave 64 Gaussians adjacent in
+// Morton (sorted-leaf) order and a chunk of consecutive directions, a pool of
+// rays that its lanes drain (see the pooled traversal below). The adjoint
+// gives each lane one Gaussian's chunk of S directions, traced one after the
+// other. Either way ~16M lanes' worth of work items let the hardware
+// dispatcher balance the skewed per-ray work across many waves instead of
+// waiting on the slowest Gaussian. Blocks are renumbered so that each XCD
+// (round-robin dispatch) walks a contiguous range of the Morton order and its
+// L2 sees a compact part of the tree. Per-Gaussian sums are FP64 partials per
+// chunk, added in chunk order by a second kernel (deterministic, no atomics).
 #include "trace_core.h"
 
 namespace rv {
@@ -87,46 +87,6 @@ __device__ __forceinline__ bool lane_work(const ChunkMap &cm, int64_t &m, int &c
     return true;
 }
 
-template <bool kCount>
-__global__ __launch_bounds__(kTraceBlock) void k_trace_chunks(const float4 *__restrict__ nodes,
-                                                              const float4 *__restrict__ rec,
-                                                              const float4 *__restrict__ origins,
-                                                              const float *__restrict__ dirs, ChunkMap cm, Cuts c,
-                                                              float *__restrict__ vis_ray,
-                                                              double *__restrict__ partial,
-                                                              unsigned long long *__restrict__ totals) {
-    __shared__ int32_t lds[kRing * kTraceBlock];
-    int64_t m;
-    int chunk, k0, k1;
-    if (!lane_work(cm, m, chunk, k0, k1)) return;
-    const Origin g = load_origin(rec, origins, m, c);
-    RayState<kRing> rs;
-    int32_t spill[RingStack<kRing>::kSpill];
-    rs.st.lds = lds + threadIdx.x;
-    rs.st.spill = spill;
-    rs.st.stride = kTraceBlock;
-    NoHit none;
-    int64_t cn = 0, cl = 0, ch = 0;
-    double sum = 0.0;
-    int k = k0;
-    rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, (int32_t)m, cm.n);
-    while (true) {
-        const bool done = rs.node < 0 || rs.template step<NoHit, kCount>(nodes, rec, c, none, &cn, &cl, &ch);
-        if (done) {
-            if (vis_ray) vis_ray[(int64_t)g.src * cm.K + k] = rs.T;
-            sum += (double)rs.T;
-            if (++k == k1) break;
-            rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, (int32_t)m, cm.n);
-        }
-    }
-    if (partial) partial[(int64_t)chunk * cm.n + g.src] = sum;
-    if (kCount) {
-        atomicAdd(totals + 0, (unsigned long long)cn);
-        atomicAdd(totals + 1, (unsigned long long)cl);
-        atomicAdd(totals + 2, (unsigned long long)ch);
-    }
-}
-
 // ---- pooled traversal -----------------------------------------------------------
 //
 // A wave owns a pool of rays: 64 Gaussians adjacent in sorted order times a
@@ -161,7 +121,7 @@ inline PoolMap make_pool(int64_t n, int K) {
 }
 
 template <bool kCount>
-__global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__restrict__ nodes,
+__global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__restrict__ nodes4,
                                                             const float4 *__restrict__ rec,
                                                             const float4 *__restrict__ origins,
                                                             const float *__restrict__ dirs, PoolMap pm, Cuts c,
@@ -233,44 +193,43 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
         }
         if (__ballot(has) == 0) break;
 
-        // node phase: one internal node per lane with traversal work and FIFO room
-        const bool can_node = has && node >= 0 && fcount <= kFifo - 2;
+        // node phase: one four-wide node per lane with traversal work and FIFO
+        // room for all four children
+        const bool can_node = has && node >= 0 && fcount <= kFifo - 4;
         if (can_node) {
             if (--budget < 0) {
                 node = -1;
                 fcount = 0;
                 T = __int_as_float(0x7fc00000);
             } else {
-                const float4 a = nodes[4 * node + 0];
-                const float4 b = nodes[4 * node + 1];
-                const float4 cc = nodes[4 * node + 2];
-                const float4 ids = nodes[4 * node + 3];
-                const int32_t left = __float_as_int(ids.x), right = __float_as_int(ids.y);
-                const bool hl = slab_hit(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, tmin);
-                const bool hr = slab_hit(b.z, b.w, cc.x, cc.y, cc.z, cc.w, o, inv, tmin);
+                int32_t id[4];
+                visit4(nodes4, node, o, inv, tmin, id);
                 if (kCount) ++cn;
-                if (hl && left < 0) {
-                    my_fifo[((fhead + fcount) & (kFifo - 1)) * kTraceBlock] = ~left;
-                    ++fcount;
-                }
-                if (hr && right < 0) {
-                    my_fifo[((fhead + fcount) & (kFifo - 1)) * kTraceBlock] = ~right;
-                    ++fcount;
-                }
-                const bool gl = hl && left >= 0, gr = hr && right >= 0;
-                if (gl && gr) {
-                    if (st.full()) {
-                        node = -1;
-                        fcount = 0;
-                        T = __int_as_float(0x7fc00000);
-                    } else {
-                        st.push(right);
-                        node = left;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    if (is_leaf(id[s])) {
+                        my_fifo[((fhead + fcount) & (kFifo - 1)) * kTraceBlock] = ~id[s];
+                        ++fcount;
                     }
-                } else if (gl) {
-                    node = left;
-                } else if (gr) {
-                    node = right;
+                }
+                int32_t nxt = -1;
+                bool overflow = false;
+#pragma unroll
+                for (int s = 3; s >= 0; --s) {
+                    if (id[s] >= 0) {
+                        if (nxt >= 0) {
+                            if (st.full()) overflow = true;
+                            else st.push(nxt);
+                        }
+                        nxt = id[s];
+                    }
+                }
+                if (overflow) {
+                    node = -1;
+                    fcount = 0;
+                    T = __int_as_float(0x7fc00000);
+                } else if (nxt >= 0) {
+                    node = nxt;
                 } else if (!st.empty()) {
                     node = st.pop();
                 } else {
@@ -282,8 +241,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
         // leaf phase: test one pending leaf per lane when enough lanes have one,
         // when a lane cannot traverse for lack of FIFO room, or when no lane can traverse
         const uint64_t pend = __ballot(has && fcount > 0);
-        const uint64_t blocked = __ballot(has && fcount > kFifo - 2);
-        const uint64_t trav = __ballot(has && node >= 0 && fcount <= kFifo - 2);
+        const uint64_t blocked = __ballot(has && fcount > kFifo - 4);
+        const uint64_t trav = __ballot(has && node >= 0 && fcount <= kFifo - 4);
         if (pend != 0 && (__popcll(pend) >= kLeafMin || blocked != 0 || trav == 0)) {
             if (has && fcount > 0) {
                 const int32_t leaf = my_fifo[fhead * kTraceBlock];
@@ -341,7 +300,7 @@ __global__ __launch_bounds__(256) void k_mean_from_partials(const double *__rest
 
 // One lane per listed ray; origin data recomputed from the input arrays with
 // the same operations as the leaf preparation, so results match bit for bit.
-__global__ __launch_bounds__(kTraceBlock) void k_trace_list(const float4 *__restrict__ nodes,
+__global__ __launch_bounds__(kTraceBlock) void k_trace_list(const float4 *__restrict__ nodes4,
                                                             const float4 *__restrict__ rec,
                                                             const float *__restrict__ mean,
                                                             const float *__restrict__ normal,
@@ -377,7 +336,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_list(const float4 *__rest
     NoHit none;
     rs.start(mk(mean[3 * i], mean[3 * i + 1], mean[3 * i + 2]), ray_direction(dirs, k, c.dir_mode, nrm, b1, b2),
              c.tmin_scale * smax, (int32_t)i, -1, n);
-    while (rs.node >= 0 && !rs.step(nodes, rec, c, none)) {
+    while (rs.node >= 0 && !rs.step(nodes4, rec, c, none)) {
     }
     out[s] = rs.T;
 }
@@ -407,7 +366,7 @@ struct GradScatter {
 };
 
 __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
-    const float4 *__restrict__ nodes, const float4 *__restrict__ rec, const float4 *__restrict__ origins,
+    const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float4 *__restrict__ origins,
     const float *__restrict__ dirs, ChunkMap cm, Cuts c, const float *__restrict__ grad_ray,
     const float *__restrict__ grad_mean_in, const float *__restrict__ vis_fwd, float *go, float *gm, float *gl) {
     __shared__ int32_t lds[kRing * kTraceBlock];
@@ -453,14 +412,14 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
         bool done;
         if (phase == 0) {
             // first pass: the ray's final T (same traversal, same early exit)
-            done = rs.node < 0 || rs.step(nodes, rec, c, none);
+            done = rs.node < 0 || rs.step(nodes4, rec, c, none);
             if (done) {
                 gs.g_over = -gk * rs.T;
                 rs.start(rs.o, rs.d, rs.tmin, rs.self, rs.self_leaf, cm.n);
                 phase = 1;
             }
         } else {
-            done = rs.node < 0 || rs.step(nodes, rec, c, gs);
+            done = rs.node < 0 || rs.step(nodes4, rec, c, gs);
             if (done) live = begin_ray(k + 1);
         }
     }
@@ -526,7 +485,7 @@ extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g,
     const Cuts c = make_cuts(*p);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_trace_pool<false>, dim3((unsigned)pm.n_blocks), dim3(kTraceBlock), 0, s,
-                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, pm, c,
+                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, pm, c,
                        vis_ray, partial, (unsigned long long *)nullptr);
     if (vis_mean)
         hipLaunchKernelGGL(k_mean_from_partials, dim3(grid_for(g->n, 256)), dim3(256), 0, s, partial, g->n,
@@ -550,7 +509,7 @@ extern "C" rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, cons
     hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(totals), (int64_t)6,
                        0u);
     hipLaunchKernelGGL(k_trace_pool<true>, dim3((unsigned)pm.n_blocks), dim3(kTraceBlock), 0, s,
-                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, pm, c,
+                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, pm, c,
                        (float *)nullptr, (double *)nullptr, (unsigned long long *)totals);
     return check_launch("rv_trace_stats");
 }
@@ -567,7 +526,7 @@ extern "C" rv_status rv_trace_rays(const void *bvh, const rv_gaussians *g, const
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
     hipLaunchKernelGGL(k_trace_list, dim3(grid_for(n_rays, kTraceBlock)), dim3(kTraceBlock), 0, (hipStream_t)stream,
-                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), g->mean, p->dir_mode ? g->normal : nullptr,
+                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean, p->dir_mode ? g->normal : nullptr,
                        g->log_scale, g->n, dirs, K, c, ray_ids, n_rays, out);
     return check_launch("rv_trace_rays");
 }
@@ -588,7 +547,7 @@ extern "C" rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaus
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
     hipLaunchKernelGGL(k_trace_backward, dim3((unsigned)cm.n_blocks), dim3(kTraceBlock), 0, (hipStream_t)stream,
-                       at<float4>(bvh, L.nodes), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, cm, c,
+                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, cm, c,
                        grad_vis_ray, grad_vis_mean, vis_ray_fwd, grad_opacity, grad_mean, grad_log_scale);
     return check_launch("rv_trace_visibility_backward");
 }

@@ -1,10 +1,12 @@
 // trace_core.h -- per-lane all-hit BVH traversal of one ray through 3D
-// Gaussians (Sec. 4.1): starting at the root, test both children's boxes,
+// Gaussians (Sec. 4.1): starting at the root, test the children's boxes,
 // descend into the hit ones, and at each leaf evaluate the Gaussian at its
 // equivalent intersection point (Eq. (13), peak parameter Eq. (14) with
 // Sigma^-1) and attenuate T by (1 - alpha) (Eq. (15)); stop early once
-// T < T_min. The order of hits does not matter for T (Sec. 4.1), so children
-// are visited left first without sorting by distance.
+// T < T_min. The tree is walked through its compressed four-wide records
+// (each internal node lists its grandchildren). The order of hits does not
+// change the full product (Sec. 4.1), so children are taken in slot order
+// without sorting by distance.
 #pragma once
 
 #include "rv_internal.h"
@@ -14,6 +16,9 @@ namespace rv {
 // Deepest possible root-to-leaf path: each level consumes at least one bit of
 // the 95-bit augmented key (63-bit Morton key + 32-bit position).
 constexpr int kMaxDepth = 96;
+// Stack bound of the four-wide walk: at most 48 wide levels on a path, each
+// leaving at most three siblings on the stack.
+constexpr int kMaxStack = 3 * (kMaxDepth / 2);
 
 struct Cuts {
     float alpha_min, alpha_max, T_stop, q_cut, tmin_scale;
@@ -59,21 +64,42 @@ __device__ __forceinline__ f3 safe_inv(f3 d) {
     return mk(r(d.x), r(d.y), r(d.z));
 }
 
-// Conservative slab test of the ray segment [t0, inf) against a box: the
-// differences are taken before scaling and the exit distance is enlarged by
-// (1 + 2 gamma_3) (Ize, "Robust BVH Ray Traversal", JCGT 2013), so a box the
-// exact ray enters is never rejected by rounding. (The builder also widens
-// every leaf box by 2^-20 of the scene scale.) The FMA form lo/d - o/d saves
-// six instructions per box but costs registers and measured slower.
-__device__ __forceinline__ bool slab_hit(float lx, float ly, float lz, float hx, float hy, float hz, f3 o, f3 inv,
-                                         float t0) {
-    const float ax = (lx - o.x) * inv.x, bx = (hx - o.x) * inv.x;
-    const float ay = (ly - o.y) * inv.y, by = (hy - o.y) * inv.y;
-    const float az = (lz - o.z) * inv.z, bz = (hz - o.z) * inv.z;
-    const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t0));
-    const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
-    return tn <= tf * 1.0000004f;
+// Children of compressed four-wide node `node` whose boxes the ray segment
+// [t0, inf) enters, in slot order; missed and unused slots come out as
+// kEmptyChild. A box plane is O_a + q step_a (q one byte), so its ray
+// distance is fma(q, step_a / d_a, (O_a - o_a) / d_a); step_a / d_a is exact,
+// and the two roundings of (O_a - o_a) / d_a and the one of the fma stay far
+// below the outward margin the builder added to every plane. The exit
+// distance is further enlarged by (1 + 2 gamma_3) for the rounding of 1/d
+// (Ize, "Robust BVH Ray Traversal", JCGT 2013). So a box the exact ray
+// enters beyond t0 is never rejected.
+__device__ __forceinline__ void visit4(const float4 *__restrict__ nodes4, int32_t node, f3 o, f3 inv, float t0,
+                                       int32_t (&id)[4]) {
+    const uint4 *r = reinterpret_cast<const uint4 *>(nodes4) + 4 * (int64_t)node;
+    const uint4 w0 = r[0], w1 = r[1], w2 = r[2];
+    const uint32_t meta = w0.w;
+    const float ax = __uint_as_float((meta & 0xffu) << 23) * inv.x;
+    const float ay = __uint_as_float(((meta >> 8) & 0xffu) << 23) * inv.y;
+    const float az = __uint_as_float(((meta >> 16) & 0xffu) << 23) * inv.z;
+    const float bx = (__uint_as_float(w0.x) - o.x) * inv.x;
+    const float by = (__uint_as_float(w0.y) - o.y) * inv.y;
+    const float bz = (__uint_as_float(w0.z) - o.z) * inv.z;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        auto q = [j](uint32_t w) { return (float)((w >> (8 * j)) & 0xffu); };
+        const float lx = fmaf(q(w1.x), ax, bx), hx = fmaf(q(w1.w), ax, bx);
+        const float ly = fmaf(q(w1.y), ay, by), hy = fmaf(q(w2.x), ay, by);
+        const float lz = fmaf(q(w1.z), az, bz), hz = fmaf(q(w2.y), az, bz);
+        const float tn = fmaxf(fmaxf(fminf(lx, hx), fminf(ly, hy)), fmaxf(fminf(lz, hz), t0));
+        const float tf = fminf(fminf(fmaxf(lx, hx), fmaxf(ly, hy)), fmaxf(lz, hz));
+        const uint32_t kind = (meta >> (24 + 2 * j)) & 3u;
+        const int32_t idx = (int32_t)(j < 2 ? w2.z : w2.w) + (j & 1);
+        const bool hit = kind != 0u && tn <= tf * 1.0000004f;
+        id[j] = !hit ? kEmptyChild : (kind == 2u ? ~idx : idx);
+    }
 }
+
+__device__ __forceinline__ bool is_leaf(int32_t id) { return id < 0 && id != kEmptyChild; }
 
 // What a leaf test hands to a hit callback.
 struct LeafHit {
@@ -148,7 +174,7 @@ __device__ __forceinline__ float leaf_factor(const float4 *__restrict__ rec, int
 // live in the ring at slot (index % kRing), entries [0, sp - kRing) in spill[].
 template <int kRing>
 struct RingStack {
-    static constexpr int kSpill = kMaxDepth - kRing;
+    static constexpr int kSpill = kMaxStack - kRing;
     int32_t *lds;   // this lane's column: lds[slot * stride]
     int32_t *spill; // private array of kSpill entries
     int stride;
@@ -156,7 +182,7 @@ struct RingStack {
 
     __device__ __forceinline__ void reset() { sp = 0; }
     __device__ __forceinline__ bool empty() const { return sp == 0; }
-    __device__ __forceinline__ bool full() const { return sp >= kMaxDepth; }
+    __device__ __forceinline__ bool full() const { return sp >= kMaxStack; }
     __device__ __forceinline__ void push(int32_t x) {
         const int slot = sp & (kRing - 1);
         if (sp >= kRing) spill[sp - kRing] = lds[slot * stride];
@@ -172,7 +198,7 @@ struct RingStack {
     }
 };
 
-// One ray's traversal state; step() processes one internal node.
+// One ray's traversal state; step() processes one four-wide node.
 template <int kRing>
 struct RayState {
     f3 o, d, inv;   // origin, unit direction, 1/d
@@ -204,48 +230,43 @@ struct RayState {
         return true;
     }
 
-    // Visit `node`; returns true when the ray is finished.
+    // Visit four-wide node `node`: test its hit leaves in slot order (the exit
+    // checked after each), then continue with the first hit internal child,
+    // stacking the others so that they come off in slot order. Returns true
+    // when the ray is finished.
     template <class OnHit, bool kCount = false>
-    __device__ __forceinline__ bool step(const float4 *__restrict__ nodes, const float4 *__restrict__ rec,
+    __device__ __forceinline__ bool step(const float4 *__restrict__ nodes4, const float4 *__restrict__ rec,
                                          const Cuts &c, OnHit &on_hit, int64_t *n_nodes = nullptr,
                                          int64_t *n_leaves = nullptr, int64_t *n_hits = nullptr) {
         if (--budget < 0) return fail();
-        const float4 a = nodes[4 * node + 0];
-        const float4 b = nodes[4 * node + 1];
-        const float4 cc = nodes[4 * node + 2];
-        const float4 ids = nodes[4 * node + 3];
-        const int32_t left = __float_as_int(ids.x), right = __float_as_int(ids.y);
-        const bool hl = slab_hit(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, tmin);
-        const bool hr = slab_hit(b.z, b.w, cc.x, cc.y, cc.z, cc.w, o, inv, tmin);
+        int32_t id[4];
+        visit4(nodes4, node, o, inv, tmin, id);
         if (kCount) ++*n_nodes;
-        // leaves in discovery order, the exit checked after each (T < T_min)
-        if (hl && left < 0) {
-            const float f = leaf_factor(rec, ~left, o, d, tmin, self, self_leaf, c, on_hit, T);
-            if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
-            T *= f;
-            if (T < c.T_stop) {
-                node = -1;
-                return true;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (is_leaf(id[s])) {
+                const float f = leaf_factor(rec, ~id[s], o, d, tmin, self, self_leaf, c, on_hit, T);
+                if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
+                T *= f;
+                if (T < c.T_stop) {
+                    node = -1;
+                    return true;
+                }
             }
         }
-        if (hr && right < 0) {
-            const float f = leaf_factor(rec, ~right, o, d, tmin, self, self_leaf, c, on_hit, T);
-            if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
-            T *= f;
-            if (T < c.T_stop) {
-                node = -1;
-                return true;
+        int32_t nxt = -1;
+#pragma unroll
+        for (int s = 3; s >= 0; --s) {
+            if (id[s] >= 0) {
+                if (nxt >= 0) {
+                    if (st.full()) return fail();
+                    st.push(nxt);
+                }
+                nxt = id[s];
             }
         }
-        const bool gl = hl && left >= 0, gr = hr && right >= 0;
-        if (gl && gr) {
-            if (st.full()) return fail();
-            st.push(right);
-            node = left;
-        } else if (gl) {
-            node = left;
-        } else if (gr) {
-            node = right;
+        if (nxt >= 0) {
+            node = nxt;
         } else if (!st.empty()) {
             node = st.pop();
         } else {

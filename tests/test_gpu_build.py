@@ -1,6 +1,8 @@
 """GPU LBVH build vs the oracle: Morton keys, sort order and radix-tree topology
 bit-exact; leaf boxes conservative and tight against the FP64 3-sigma boxes;
-internal boxes the exact union of their children; repeated builds identical."""
+internal boxes the exact union of their children; compressed four-wide records
+list the grandchildren of each node with outward-rounded boxes; repeated builds
+identical."""
 import math
 
 import numpy as np
@@ -21,6 +23,57 @@ def _build(scene):
     bvh = build_bvh(g)
     torch.cuda.synchronize()
     return g, bvh, bvh.arrays()
+
+
+def check_nodes4(A):
+    """Compressed four-wide records: slot kinds and indices are the
+    grandchildren of each node (a leaf child keeps its own slot, the next is
+    empty); every decoded plane O + q step lies outside the child's binary box
+    by at least the margin eta and by at most eta plus one step."""
+    W = A["nodes4"]
+    m = W.shape[0]
+    assert np.all(W[:, 12:16] == 0)
+    meta = W[:, 3]
+    kind = np.stack([(meta >> (24 + 2 * j)) & 3 for j in range(4)], 1)
+    idx = np.stack([W[:, 10].view(np.int32), W[:, 10].view(np.int32) + 1,
+                    W[:, 11].view(np.int32), W[:, 11].view(np.int32) + 1], 1)
+    exp_kind = np.zeros((m, 4), np.uint32)
+    exp_idx = np.zeros((m, 4), np.int64)
+    boxes = np.zeros((m, 4, 6), np.float64)
+    for side, (ch, cbox) in enumerate(((A["left"], A["left_box"]), (A["right"], A["right_box"]))):
+        leaf = ch < 0
+        s0, s1 = 2 * side, 2 * side + 1
+        exp_kind[leaf, s0] = 2
+        exp_idx[leaf, s0] = ~ch[leaf]
+        boxes[leaf, s0] = cbox[leaf]
+        inner = np.nonzero(~leaf)[0]
+        c = ch[inner]
+        lc, rc = A["left"][c], A["right"][c]
+        exp_kind[inner, s0] = np.where(lc < 0, 2, 1)
+        exp_kind[inner, s1] = np.where(rc < 0, 2, 1)
+        exp_idx[inner, s0] = np.where(lc < 0, ~lc, lc)
+        exp_idx[inner, s1] = np.where(rc < 0, ~rc, rc)
+        boxes[inner, s0] = A["left_box"][c]
+        boxes[inner, s1] = A["right_box"][c]
+    assert np.array_equal(kind, exp_kind), "slot kinds differ from the grandchildren"
+    used = exp_kind != 0
+    assert np.array_equal(idx[used], exp_idx[used]), "slot indices differ from the grandchildren"
+    root = A["header"][6:12].astype(np.float64)
+    eta = (np.abs(root).max() + np.linalg.norm(root[3:] - root[:3]) + 1.0) * 2.0 ** -20
+    O = W[:, 0:3].view(np.float32).astype(np.float64)
+    step = np.stack([2.0 ** (((meta >> (8 * a)) & 0xFF).astype(np.float64) - 127) for a in range(3)], 1)
+    for a in range(3):
+        qlo = np.stack([(W[:, 4 + a] >> (8 * j)) & 0xFF for j in range(4)], 1).astype(np.float64)
+        qhi = np.stack([(W[:, 7 + a] >> (8 * j)) & 0xFF for j in range(4)], 1).astype(np.float64)
+        dlo = O[:, a:a + 1] + qlo * step[:, a:a + 1]
+        dhi = O[:, a:a + 1] + qhi * step[:, a:a + 1]
+        lo, hi = boxes[:, :, a], boxes[:, :, 3 + a]
+        tol = 1e-12 * (np.abs(lo) + np.abs(hi) + 1.0) + np.abs(O[:, a:a + 1]) * 2.0 ** -23
+        assert np.all((dlo <= lo - eta + tol)[used]) and np.all((dhi >= hi + eta - tol)[used]), \
+            f"a decoded plane cuts into its child box (axis {a})"
+        slack = eta + step[:, a:a + 1] + tol
+        assert np.all((lo - dlo <= slack)[used]) and np.all((dhi - hi <= slack)[used]), \
+            f"decoded planes not tight (axis {a})"
 
 
 def check_build(scene, label=""):
@@ -61,6 +114,7 @@ def check_build(scene, label=""):
             assert np.array_equal(slot[leaf], A["leaf_boxes"][~ch[leaf]])
             assert np.array_equal(slot[~leaf], node_box[ch[~leaf]])
         root = node_box[0]
+        check_nodes4(A)
     else:
         root = A["leaf_boxes"][0]
     allb = np.concatenate([A["leaf_boxes"][:, 0:3].min(0), A["leaf_boxes"][:, 3:6].max(0)])
