@@ -96,10 +96,11 @@ typedef struct rv_bvh_arrays {
     const uint32_t *perm;       /* [n]   sorted position -> original index */
     const float *nodes;         /* [n-1][16] internal nodes, see below */
     const int32_t *parent;      /* [2n-1] parent of internal node i at i, of leaf m at n-1+m; root -1 */
-    const float *leaf_records;  /* [n][16] per sorted leaf: mu[3], o, W row0[3], src, W row1[3], pad, W row2[3], pad */
+    const float *leaf_records;  /* [n][12] per sorted leaf: mu[3], o, W row0[3], s0 s1/s2, W row1[3], src;
+                                   W = diag(1/s) R^T, row 2 = (s0 s1/s2) (row0 x row1) */
     const float *leaf_boxes;    /* [n][6]  per sorted leaf: lo[3], hi[3] (3-sigma box, widened outward) */
     const float *origins;       /* [n][4]  per sorted leaf: unit normal[3], t_min */
-    const float *nodes4;        /* [n-1][32] four-wide node per internal node, see rv_build_bvh */
+    const uint32_t *nodes4;     /* [n-1][16] compressed four-wide node per internal node, see rv_build_bvh */
 } rv_bvh_arrays;
 
 /* const char* describing the last failure on the calling thread ("" if none). */
@@ -129,12 +130,17 @@ size_t rv_build_workspace_bytes(int64_t n);
  * internal id, or ~m for leaf m); per-leaf records in sorted order; bottom-up
  * refit of the 3-sigma boxes. Node record (16 floats): left-child box lo[3],
  * hi[3], right-child box lo[3], hi[3], then the left and right child ids as
- * int32 bit patterns, then 2 unused words. Four-wide record of internal
- * node i (32 floats, the one the tracer walks): the children of i's two
- * children, with a leaf child kept in its own slot and the next slot empty
- * (id INT32_MIN): lo_x[4], lo_y[4], lo_z[4], hi_x[4], hi_y[4], hi_z[4],
- * child ids[4] as int32 bit patterns, 4 unused words; boxes copied bit for
- * bit from the binary records.
+ * int32 bit patterns, then 2 unused words. Compressed four-wide record of
+ * internal node i (16 words, the one the tracer walks) lists the children of
+ * i's two children; a leaf child keeps its own slot and the next slot is
+ * empty. Words 0-2: origin O (float); word 3: bytes 0-2 per-axis step
+ * exponents (step_a = 2^(byte - 127)), byte 3 the kind of slot j in bits
+ * 2j..2j+1 (0 empty, 1 internal node, 2 leaf); words 4-9: lo_x, lo_y, lo_z,
+ * hi_x, hi_y, hi_z planes, byte j for slot j, plane = O_a + byte * step_a;
+ * words 10-11: index of slot 2s for side s (slot 2s + 1 holds index + 1);
+ * words 12-15 zero. Planes lie outside the binary child boxes by at least
+ * eta = (largest root-box coordinate + root diagonal + 1) * 2^-20 and by at
+ * most eta + one step.
  * The result depends only on the inputs (bit-identical across runs).
  * Errors: RV_ERR_INVALID_ARG (null pointers, n < 1, n > RV_MAX_GAUSSIANS,
  * unaligned bvh), RV_ERR_WORKSPACE (bvh_bytes or ws_bytes too small),

@@ -232,10 +232,11 @@ __global__ __launch_bounds__(256) void k_leaf_prep(const float *__restrict__ mea
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) W[a][c] = is[a] * R[c][a];
-    rec[4 * m + 0] = make_float4(mu[0], mu[1], mu[2], opacity[i]);
-    rec[4 * m + 1] = make_float4(W[0][0], W[0][1], W[0][2], __int_as_float((int)i));
-    rec[4 * m + 2] = make_float4(W[1][0], W[1][1], W[1][2], 0.0f);
-    rec[4 * m + 3] = make_float4(W[2][0], W[2][1], W[2][2], 0.0f);
+    // row 2 of W is not stored: for a proper rotation, column 2 of R is
+    // column 0 x column 1, so W row 2 = (s0 s1 / s2) (W row 0 x W row 1)
+    rec[kLeafF4 * m + 0] = make_float4(mu[0], mu[1], mu[2], opacity[i]);
+    rec[kLeafF4 * m + 1] = make_float4(W[0][0], W[0][1], W[0][2], s[0] * s[1] * is[2]);
+    rec[kLeafF4 * m + 2] = make_float4(W[1][0], W[1][1], W[1][2], __int_as_float((int)i));
     // 3-sigma box: half extent along world axis a is 3 sqrt(sum_m (R_am s_m)^2),
     // widened by a relative 2^-12 (rounding of R, s and the square root) and by
     // 2^-20 of the scene scale (rounding of the box and of the slab test)
@@ -496,7 +497,7 @@ extern "C" rv_status rv_bvh_view(const void *bvh, int64_t n, rv_bvh_arrays *out)
     out->leaf_records = at<float>(bvh, L.leaf_rec);
     out->leaf_boxes = at<float>(bvh, L.leaf_box);
     out->origins = at<float>(bvh, L.origins);
-    out->nodes4 = at<float>(bvh, L.nodes4);
+    out->nodes4 = at<uint32_t>(bvh, L.nodes4);
     return RV_OK;
 }
 

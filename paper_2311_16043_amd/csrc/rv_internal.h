@@ -46,6 +46,9 @@ constexpr int kHeaderFloats = 16;
 constexpr int32_t kEmptyChild = INT32_MIN;
 // Bytes per compressed four-wide node (48 used).
 constexpr size_t kNode4Bytes = 64;
+// Leaf record, three float4 per sorted leaf: (mu, opacity), (W row 0,
+// s0 s1 / s2), (W row 1, source index bits); W row 2 = (s0 s1 / s2) (row 0 x row 1).
+constexpr int kLeafF4 = 3;
 
 struct BvhLayout {
     size_t header, keys, perm, nodes, parent, leaf_rec, leaf_box, origins, nodes4, total;
@@ -60,7 +63,7 @@ inline BvhLayout bvh_layout(int64_t n) {
     L.perm = off; off = align_up(off + nn * 4);
     L.nodes = off; off = align_up(off + (nn > 1 ? nn - 1 : 1) * 64);
     L.parent = off; off = align_up(off + (2 * nn - 1) * 4);
-    L.leaf_rec = off; off = align_up(off + nn * 64);
+    L.leaf_rec = off; off = align_up(off + nn * 16 * kLeafF4);
     L.leaf_box = off; off = align_up(off + nn * 24);
     L.origins = off; off = align_up(off + nn * 16);
     L.nodes4 = off; off = align_up(off + (nn > 1 ? nn - 1 : 1) * kNode4Bytes);

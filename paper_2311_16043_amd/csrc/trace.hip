@@ -33,9 +33,9 @@ struct Origin {
 __device__ __forceinline__ Origin load_origin(const float4 *__restrict__ rec, const float4 *__restrict__ origins,
                                               int64_t m, const Cuts &c) {
     Origin g;
-    const float4 r0 = rec[4 * m];
+    const float4 r0 = rec[kLeafF4 * m];
     const float4 og = origins[m];
-    g.src = __float_as_int(rec[4 * m + 1].w);
+    g.src = __float_as_int(rec[kLeafF4 * m + 2].w);
     g.o = mk(r0.x, r0.y, r0.z);
     g.nrm = mk(og.x, og.y, og.z);
     g.tmin = c.tmin_scale * og.w;
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
             if (!has && idx < pool_n) {
                 const int oi = idx % nv, j = idx / nv;
                 const int64_t m = m0 + oi;
-                const float4 r0 = rec[4 * m];
+                const float4 r0 = rec[kLeafF4 * m];
                 const float4 og = origins[m];
                 const f3 nrm = mk(og.x, og.y, og.z);
                 f3 b1, b2;
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
                 d = ray_direction(dirs, k0 + j, c.dir_mode, nrm, b1, b2);
                 inv = safe_inv(d);
                 tmin = c.tmin_scale * og.w;
-                self = __float_as_int(rec[4 * m + 1].w);
+                self = __float_as_int(rec[kLeafF4 * m + 2].w);
                 self_leaf = (int32_t)m;
                 T = 1.0f;
                 st.sp = 0;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
     __builtin_amdgcn_wave_barrier();
     if (lane < nv) {
         const int64_t m = m0 + lane;
-        const int32_t src = __float_as_int(rec[4 * m + 1].w);
+        const int32_t src = __float_as_int(rec[kLeafF4 * m + 2].w);
         double sum = 0.0;
         for (int j = 0; j < s_eff; ++j) {
             const float t = tbuf[wv][j * nv + lane];

@@ -124,14 +124,14 @@ __device__ __forceinline__ float leaf_factor(const float4 *__restrict__ rec, int
                                              int32_t self, int32_t self_leaf, const Cuts &c, OnHit &on_hit,
                                              float T_before) {
     if (m == self_leaf) return 1.0f;   // the source's own leaf, known by sorted position
-    // all four rows in flight at once
-    const float4 r0 = rec[4 * m + 0];
-    const float4 r1 = rec[4 * m + 1];
-    const float4 r2 = rec[4 * m + 2];
-    const float4 r3 = rec[4 * m + 3];
-    const int32_t src = __float_as_int(r1.w);
+    // all three rows in flight at once
+    const float4 r0 = rec[kLeafF4 * m + 0];
+    const float4 r1 = rec[kLeafF4 * m + 1];
+    const float4 r2 = rec[kLeafF4 * m + 2];
+    const int32_t src = __float_as_int(r2.w);
     if (src == self) return 1.0f;      // the source, when its sorted position is not known
-    const f3 w0 = mk(r1.x, r1.y, r1.z), w1 = mk(r2.x, r2.y, r2.z), w2 = mk(r3.x, r3.y, r3.z);
+    const f3 w0 = mk(r1.x, r1.y, r1.z), w1 = mk(r2.x, r2.y, r2.z);
+    const f3 w2 = r1.w * cross(w0, w1);
     const f3 x = o - mk(r0.x, r0.y, r0.z);
     const f3 p = mk(dot(w0, x), dot(w1, x), dot(w2, x));
     const f3 v = mk(dot(w0, d), dot(w1, d), dot(w2, d));

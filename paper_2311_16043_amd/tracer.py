@@ -119,7 +119,7 @@ class BVH:
             left_box=nodes[:, 0:6].copy(),
             right_box=nodes[:, 6:12].copy(),
             parent=grab(v.parent, 2 * n - 1, np.int32),
-            leaf_records=grab(v.leaf_records, 16 * n, np.float32).reshape(n, 16),
+            leaf_records=grab(v.leaf_records, 12 * n, np.float32).reshape(n, 12),
             leaf_boxes=grab(v.leaf_boxes, 6 * n, np.float32).reshape(n, 6),
             origins=grab(v.origins, 4 * n, np.float32).reshape(n, 4),
             nodes4=grab(v.nodes4, 16 * max(n - 1, 0), np.uint32).reshape(-1, 16),

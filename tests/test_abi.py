@@ -54,10 +54,11 @@ def test_bvh_view_offsets_are_aligned_and_ordered(lib):
     base = 1 << 40  # never dereferenced
     out = _lib.RvBvhArrays()
     assert lib.rv_bvh_view(base, 1000, C.byref(out)) == 0
-    ptrs = [out.header, out.keys, out.perm, out.nodes, out.parent, out.leaf_records, out.leaf_boxes, out.origins]
+    ptrs = [out.header, out.keys, out.perm, out.nodes, out.parent, out.leaf_records, out.leaf_boxes, out.origins,
+            out.nodes4]
     assert all(p % 256 == 0 for p in ptrs)
     assert ptrs == sorted(ptrs) and ptrs[0] == base
-    assert ptrs[-1] + 1000 * 16 <= base + lib.rv_bvh_bytes(1000)
+    assert ptrs[-1] + 999 * 64 <= base + lib.rv_bvh_bytes(1000)
     assert lib.rv_bvh_view(None, 10, C.byref(out)) == _lib.RV_ERR_INVALID_ARG
     assert lib.rv_bvh_view(base, 0, C.byref(out)) == _lib.RV_ERR_INVALID_ARG
 

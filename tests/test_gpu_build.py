@@ -90,9 +90,18 @@ def check_build(scene, label=""):
     assert np.array_equal(A["parent"], O["parent"]), "parents differ"
     # leaf records carry the source index and opacity in sorted order
     rec = A["leaf_records"]
-    assert np.array_equal(rec[:, 7].view(np.int32).astype(np.int64), O["order"])
+    assert np.array_equal(rec[:, 11].view(np.int32).astype(np.int64), O["order"])
     assert np.array_equal(rec[:, 3], scene["opacity"][O["order"]])
     assert np.array_equal(rec[:, 0:3], scene["mean"][O["order"]])
+    # whitening rows 0 and 1 as stored, row 2 as the tracer rebuilds it
+    # (s0 s1 / s2 times row 0 x row 1), against the FP64 W = diag(1/s) R^T
+    w0, w1 = rec[:, 4:7].astype(np.float64), rec[:, 8:11].astype(np.float64)
+    w2 = rec[:, 7:8].astype(np.float64) * np.cross(w0, w1)
+    for k in np.linspace(0, n - 1, min(n, 200)).astype(np.int64):
+        i = O["order"][k]
+        Wo = oracle.whitening(scene["quat"][i], scene["log_scale"][i])
+        Wg = np.stack([w0[k], w1[k], w2[k]])
+        assert np.allclose(Wg, Wo, rtol=0, atol=2e-6 * np.abs(Wo).max()), (k, Wg, Wo)
     # leaf boxes: contain the FP64 3-sigma box, and are tight
     llo, lhi = oracle.leaf_boxes(scene)
     olo, ohi = llo[O["order"]], lhi[O["order"]]
