@@ -66,6 +66,8 @@ def parse():
     return ap.parse_args()
 
 
+NODE_BYTES = 48   # compressed four-wide node: origin, exponents and kinds, 24 plane bytes, 2 child indices
+LEAF_BYTES = 48   # leaf record: mean, opacity, two whitening rows, s0 s1/s2, source index
 MLP_FLOPS_PER_QUERY = 2 * (64 * 256 + 3 * 256 * 256 + 256 * 2)   # dense layers, padded input width 64
 BF16_PEAK_TFLOPS = 2500.0
 
@@ -237,10 +239,10 @@ def main():
     value = rays * args.steps / wall
 
     # algorithmic bytes of the traversal kernel (deterministic for this BVH):
-    # origin data, one 128-byte four-wide record per node visit, one 64-byte
+    # origin data, one compressed four-wide record per node visit, one leaf
     # record per leaf test, the ray's output, and the mean per Gaussian
     st = trace_stats(bvh, g, dirs, prm)
-    alg_bytes = 24 * rays + 128 * st["nodes"] + 64 * st["leaves"] + 4 * rays + 4 * n
+    alg_bytes = 24 * rays + NODE_BYTES * st["nodes"] + LEAF_BYTES * st["leaves"] + 4 * rays + 4 * n
     trace_s = float(np.mean(trace_ms)) / 1000.0
     achieved = alg_bytes / trace_s / 1e9
     print(f"[bench] step {ms_per_step:.2f} ms (build {np.mean(build_ms):.3f} ms, trace {np.mean(trace_ms):.3f} ms); "
@@ -283,9 +285,9 @@ def main():
             "nodes_per_ray": st["nodes"] / rays,
             "leaves_per_ray": st["leaves"] / rays,
             "hits_per_ray": st["hits"] / rays,
-            # brute force reads every other Gaussian's 64-byte record per ray
-            "brute_force_bytes_per_ray": 64 * (n - 1),
-            "work_avoided": 64 * (n - 1) * rays / alg_bytes,
+            # brute force reads every other Gaussian's record per ray
+            "brute_force_bytes_per_ray": LEAF_BYTES * (n - 1),
+            "work_avoided": LEAF_BYTES * (n - 1) * rays / alg_bytes,
         },
     }
     if not args.no_surrogate and name != "tiny":
