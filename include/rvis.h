@@ -186,7 +186,7 @@ rv_status rv_trace_rays(const void *bvh, const rv_gaussians *g, const float *dir
 
 /*
  * Traversal statistics of rv_trace_visibility's rays: writes (device)
- * totals[0] = internal nodes visited, totals[1] = leaf records tested,
+ * totals[0] = four-wide node visits, totals[1] = leaf records tested,
  * totals[2] = Gaussians included, summed over all n*K rays (int64, overwritten).
  * Used to compute algorithmic bytes; runs a separate instrumented kernel.
  */

@@ -98,7 +98,7 @@ __device__ __forceinline__ bool lane_work(const ChunkMap &cm, int64_t &m, int &c
 // executes with most lanes active instead of inside every node step. Leaves
 // are tested in discovery (FIFO) order, so each ray's product, and its early
 // exit, is the same as a single-ray traversal's, bit for bit.
-constexpr int kPoolS = 8;
+constexpr int kPoolS = 4;
 constexpr int kFifo = 8;
 constexpr int kPoolRing = 8;
 constexpr int kLeafMin = 32;

@@ -116,20 +116,33 @@ struct NoHit {
     __device__ __forceinline__ void operator()(const LeafHit &, float) const {}
 };
 
+// e^x - 1 for x in [-1/4, 0] from its Taylor series through x^7 (the
+// remainder x^8 / 8! is below 2e-9 of the result there), evaluated in
+// Horner form; unlike e^x - 1 it keeps full relative precision as x -> 0.
+__device__ __forceinline__ float expm1_small(float x) {
+    float r = 1.0f / 5040.0f;
+    r = fmaf(r, x, 1.0f / 720.0f);
+    r = fmaf(r, x, 1.0f / 120.0f);
+    r = fmaf(r, x, 1.0f / 24.0f);
+    r = fmaf(r, x, 1.0f / 6.0f);
+    r = fmaf(r, x, 0.5f);
+    r = fmaf(r, x, 1.0f);
+    return r * x;
+}
+
 // Evaluate leaf m for the ray (o, d) of source `self`. Returns the factor
 // (1 - alpha) to multiply into T (1 when excluded); calls on_hit for included
-// Gaussians with the running T before this factor.
+// Gaussians with the running T before this factor. Branch-free up to the
+// final decision, so the record's three rows are fetched together.
 template <class OnHit>
 __device__ __forceinline__ float leaf_factor(const float4 *__restrict__ rec, int32_t m, f3 o, f3 d, float tmin,
                                              int32_t self, int32_t self_leaf, const Cuts &c, OnHit &on_hit,
                                              float T_before) {
     if (m == self_leaf) return 1.0f;   // the source's own leaf, known by sorted position
-    // all three rows in flight at once
     const float4 r0 = rec[kLeafF4 * m + 0];
     const float4 r1 = rec[kLeafF4 * m + 1];
     const float4 r2 = rec[kLeafF4 * m + 2];
     const int32_t src = __float_as_int(r2.w);
-    if (src == self) return 1.0f;      // the source, when its sorted position is not known
     const f3 w0 = mk(r1.x, r1.y, r1.z), w1 = mk(r2.x, r2.y, r2.z);
     const f3 w2 = r1.w * cross(w0, w1);
     const f3 x = o - mk(r0.x, r0.y, r0.z);
@@ -137,20 +150,23 @@ __device__ __forceinline__ float leaf_factor(const float4 *__restrict__ rec, int
     const f3 v = mk(dot(w0, d), dot(w1, d), dot(w2, d));
     const float vv = dot(v, v);
     const float pv = dot(p, v);
-    const float inv_vv = 1.0f / vv;
-    const float t = -pv * inv_vv;
-    if (!(t >= tmin)) return 1.0f;
     const f3 cp = cross(p, v);
-    const float q = dot(cp, cp) * inv_vv;
-    if (!(q <= c.q_cut)) return 1.0f;
+    const float cc = dot(cp, cp);
+    // peak parameter t* = -pv / vv >= t_min and squared distance at the peak
+    // q = |p x v|^2 / vv <= q_cut, both decided without dividing (vv > 0); the
+    // source itself (when its sorted position is not known) never counts
+    const bool in_support = src != self && -pv >= tmin * vv && cc <= c.q_cut * vv;
+    const float inv_vv = __builtin_amdgcn_rcpf(vv);
+    const float q = cc * inv_vv;
     // alpha = o e^{-q/2} = o + o m with m = e^{-q/2} - 1. For small q, m comes
-    // from expm1 so that 1 - alpha = (1 - o) - o m keeps full relative
+    // from the series so that 1 - alpha = (1 - o) - o m keeps full relative
     // precision when alpha approaches 1 (the adjoint divides by it).
     const float ex = -0.5f * q;
-    const float em1 = q < 0.5f ? expm1f(ex) : __expf(ex) - 1.0f;
+    const float m_small = expm1_small(ex), m_large = __expf(ex) - 1.0f;
+    const float em1 = q < 0.5f ? m_small : m_large;
     const float op = r0.w;
     const float alpha = op + op * em1;
-    if (!(alpha >= c.alpha_min)) return 1.0f;
+    if (!(in_support && alpha >= c.alpha_min)) return 1.0f;
     const bool clamped = alpha >= c.alpha_max;
     const float one_minus = clamped ? 1.0f - c.alpha_max : (1.0f - op) - op * em1;
     LeafHit h;
@@ -159,7 +175,7 @@ __device__ __forceinline__ float leaf_factor(const float4 *__restrict__ rec, int
     h.clamped = clamped;
     h.opacity = op;
     h.src = src;
-    h.e = p + t * v;
+    h.e = p + (-pv * inv_vv) * v;
     h.w0 = w0;
     h.w1 = w1;
     h.w2 = w2;
