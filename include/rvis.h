@@ -135,7 +135,7 @@ size_t rv_build_workspace_bytes(int64_t n);
  * i's two children; a leaf child keeps its own slot and the next slot is
  * empty. Words 0-2: origin O (float); word 3: bytes 0-2 per-axis step
  * exponents (step_a = 2^(byte - 127)), byte 3 the kind of slot j in bits
- * 2j..2j+1 (0 empty, 1 internal node, 2 leaf); words 4-9: lo_x, lo_y, lo_z,
+ * 2j..2j+1 (0 empty, 1 internal node, 3 leaf); words 4-9: lo_x, lo_y, lo_z,
  * hi_x, hi_y, hi_z planes, byte j for slot j, plane = O_a + byte * step_a;
  * words 10-11: index of slot 2s for side s (slot 2s + 1 holds index + 1);
  * words 12-15 zero. Planes lie outside the binary child boxes by at least

@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void k_refit(int64_t n, const float *__restric
 //   words 0-2   origin O (float), at or below the lowest child plane
 //   word 3      bytes 0-2: per-axis step exponents, step_a = 2^(byte - 127);
 //               byte 3: kind of slot j in bits 2j..2j+1 (0 empty, 1 internal
-//               node, 2 leaf)
+//               node, 3 leaf: bit 0 = used, bit 1 = leaf)
 //   words 4-9   lo_x, lo_y, lo_z, hi_x, hi_y, hi_z planes, one byte per slot
 //               (byte j = slot j): plane = O_a + q step_a
 //   words 10-11 index of slot 2s for side s; slot 2s + 1 holds that index + 1
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(256) void k_refit(int64_t n, const float *__restric
 // Planes are rounded outward from the refitted binary boxes after widening
 // them by eta = (largest root-box coordinate + root diagonal + 1) 2^-20, in
 // exact (double) arithmetic, so a traversal that evaluates the plane
-// distances as fma(q, step/d, (O - o)/d) (error far below eta) never rejects
+// distances as fma(q, step/d, (O - o)/d) (error below eta / 2) never rejects
 // a box the exact ray enters.
 __global__ __launch_bounds__(256) void k_collapse4(int64_t n, const float *__restrict__ nodes,
                                                    const float *__restrict__ header, float *__restrict__ nodes4) {
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void k_collapse4(int64_t n, const float *__res
                 box[s0][a] = r[6 * side + a];
                 box[s1][a] = r[6 * side + a];  // unused; keeps the node box unchanged
             }
-            kind[s0] = 2u;
+            kind[s0] = 3u;
             kind[s1] = 0u;
             base[side] = ~c;
         } else {
@@ -422,8 +422,8 @@ __global__ __launch_bounds__(256) void k_collapse4(int64_t n, const float *__res
                 box[s0][a] = rc[a];
                 box[s1][a] = rc[6 + a];
             }
-            kind[s0] = lc < 0 ? 2u : 1u;
-            kind[s1] = rcid < 0 ? 2u : 1u;
+            kind[s0] = lc < 0 ? 3u : 1u;
+            kind[s1] = rcid < 0 ? 3u : 1u;
             base[side] = lc < 0 ? ~lc : lc;
         }
     }

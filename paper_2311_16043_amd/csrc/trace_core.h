@@ -67,12 +67,12 @@ __device__ __forceinline__ f3 safe_inv(f3 d) {
 // Children of compressed four-wide node `node` whose boxes the ray segment
 // [t0, inf) enters, in slot order; missed and unused slots come out as
 // kEmptyChild. A box plane is O_a + q step_a (q one byte), so its ray
-// distance is fma(q, step_a / d_a, (O_a - o_a) / d_a); step_a / d_a is exact,
-// and the two roundings of (O_a - o_a) / d_a and the one of the fma stay far
-// below the outward margin the builder added to every plane. The exit
-// distance is further enlarged by (1 + 2 gamma_3) for the rounding of 1/d
-// (Ize, "Robust BVH Ray Traversal", JCGT 2013). So a box the exact ray
-// enters beyond t0 is never rejected.
+// distance is fma(q, step_a / d_a, (O_a - o_a) / d_a). step_a / d_a is exact;
+// the roundings of 1/d, of (O_a - o_a) / d_a and of the fma move a plane by at
+// most 2^-23 (|P - o| + |O - o|) <= 2^-21 max|coordinate| in space, which is
+// below the outward margin eta >= 2^-20 (max|coordinate| + 1) that the builder
+// added to every plane. So a box the exact ray enters beyond t0 is never
+// rejected, and no further enlargement of the exit distance is needed.
 __device__ __forceinline__ void visit4(const float4 *__restrict__ nodes4, int32_t node, f3 o, f3 inv, float t0,
                                        int32_t (&id)[4]) {
     const uint4 *r = reinterpret_cast<const uint4 *>(nodes4) + 4 * (int64_t)node;
@@ -92,10 +92,11 @@ __device__ __forceinline__ void visit4(const float4 *__restrict__ nodes4, int32_
         const float lz = fmaf(q(w1.z), az, bz), hz = fmaf(q(w2.y), az, bz);
         const float tn = fmaxf(fmaxf(fminf(lx, hx), fminf(ly, hy)), fmaxf(fminf(lz, hz), t0));
         const float tf = fminf(fminf(fmaxf(lx, hx), fmaxf(ly, hy)), fmaxf(lz, hz));
-        const uint32_t kind = (meta >> (24 + 2 * j)) & 3u;
+        // kind bits: bit 0 slot used, bit 1 leaf (~index)
+        const bool used = (meta >> (24 + 2 * j)) & 1u;
+        const int32_t leaf_mask = -(int32_t)((meta >> (25 + 2 * j)) & 1u);
         const int32_t idx = (int32_t)(j < 2 ? w2.z : w2.w) + (j & 1);
-        const bool hit = kind != 0u && tn <= tf * 1.0000004f;
-        id[j] = !hit ? kEmptyChild : (kind == 2u ? ~idx : idx);
+        id[j] = used && tn <= tf ? (idx ^ leaf_mask) : kEmptyChild;
     }
 }
 

@@ -43,14 +43,14 @@ def check_nodes4(A):
     for side, (ch, cbox) in enumerate(((A["left"], A["left_box"]), (A["right"], A["right_box"]))):
         leaf = ch < 0
         s0, s1 = 2 * side, 2 * side + 1
-        exp_kind[leaf, s0] = 2
+        exp_kind[leaf, s0] = 3
         exp_idx[leaf, s0] = ~ch[leaf]
         boxes[leaf, s0] = cbox[leaf]
         inner = np.nonzero(~leaf)[0]
         c = ch[inner]
         lc, rc = A["left"][c], A["right"][c]
-        exp_kind[inner, s0] = np.where(lc < 0, 2, 1)
-        exp_kind[inner, s1] = np.where(rc < 0, 2, 1)
+        exp_kind[inner, s0] = np.where(lc < 0, 3, 1)
+        exp_kind[inner, s1] = np.where(rc < 0, 3, 1)
         exp_idx[inner, s0] = np.where(lc < 0, ~lc, lc)
         exp_idx[inner, s1] = np.where(rc < 0, ~rc, rc)
         boxes[inner, s0] = A["left_box"][c]
