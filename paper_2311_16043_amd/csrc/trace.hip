@@ -120,36 +120,31 @@ inline PoolMap make_pool(int64_t n, int K) {
     return pm;
 }
 
-template <bool kCount>
-__global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__restrict__ nodes4,
-                                                            const float4 *__restrict__ rec,
-                                                            const float4 *__restrict__ origins,
-                                                            const float *__restrict__ dirs, PoolMap pm, Cuts c,
-                                                            float *__restrict__ vis_ray, double *__restrict__ partial,
-                                                            unsigned long long *__restrict__ totals) {
-    __shared__ int32_t stk[kPoolRing * kTraceBlock];
-    __shared__ int32_t fifo[kFifo * kTraceBlock];
-    __shared__ float tbuf[kWavesPerBlock][kPoolS * 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
-    if (w >= pm.n_items) return;  // wave-uniform
-    const int64_t grp = w / pm.n_chunks;
-    const int chunk = (int)(w - grp * pm.n_chunks);
-    const int64_t m0 = grp * 64;
-    const int nv = (int)min<int64_t>(64, pm.n - m0);
-    const int k0 = chunk * kPoolS;
-    const int s_eff = min(kPoolS, pm.K - k0);
-    const int pool_n = nv * s_eff;
-    const uint64_t lt = (1ull << lane) - 1ull;
+// One ray as a pool source hands it out.
+struct RaySetup {
+    f3 o, d;
+    float tmin;
+    int32_t self;       // original index of the source Gaussian
+    int32_t self_leaf;  // its sorted leaf position, or -1 if not known
+    bool valid;         // false: not a ray of this scene (finishes at once with NaN)
+};
 
-    // this lane's ray
+// Drain a pool of pool_n rays (setup(idx) describes ray idx) with the lanes of
+// one wave, parking each ray's final T in tbuf[idx]. stk and fifo are this
+// lane's columns of the block's LDS stack ring and leaf FIFO.
+template <bool kCount, class Setup>
+__device__ __forceinline__ void drain_pool(const float4 *__restrict__ nodes4, const float4 *__restrict__ rec,
+                                           const Cuts &c, int64_t n, int pool_n, const Setup &setup,
+                                           int32_t *stk, int32_t *my_fifo, float *tbuf, int64_t &cn, int64_t &cl,
+                                           int64_t &ch) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
     RingStack<kPoolRing> st;
     int32_t spill[RingStack<kPoolRing>::kSpill];
-    st.lds = stk + threadIdx.x;
+    st.lds = stk;
     st.spill = spill;
     st.stride = kTraceBlock;
     st.sp = 0;
-    int32_t *my_fifo = fifo + threadIdx.x;
     int fhead = 0, fcount = 0;
     bool has = false;
     int slot = 0;  // pool index of the current ray
@@ -157,7 +152,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
     float tmin = 0.f, T = 1.f;
     int32_t self = -1, self_leaf = -1, node = -1;
     int64_t budget = 0;
-    int64_t cn = 0, cl = 0, ch = 0;
     NoHit none;
     int next = 0;  // wave-uniform
 
@@ -167,25 +161,19 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
         if (need != 0 && next < pool_n) {
             const int idx = next + __popcll(need & lt);
             if (!has && idx < pool_n) {
-                const int oi = idx % nv, j = idx / nv;
-                const int64_t m = m0 + oi;
-                const float4 r0 = rec[kLeafF4 * m];
-                const float4 og = origins[m];
-                const f3 nrm = mk(og.x, og.y, og.z);
-                f3 b1, b2;
-                onb_duff(nrm, b1, b2);
-                o = mk(r0.x, r0.y, r0.z);
-                d = ray_direction(dirs, k0 + j, c.dir_mode, nrm, b1, b2);
+                const RaySetup r = setup(idx);
+                o = r.o;
+                d = r.d;
                 inv = safe_inv(d);
-                tmin = c.tmin_scale * og.w;
-                self = __float_as_int(rec[kLeafF4 * m + 2].w);
-                self_leaf = (int32_t)m;
-                T = 1.0f;
+                tmin = r.tmin;
+                self = r.self;
+                self_leaf = r.self_leaf;
+                T = r.valid ? 1.0f : __int_as_float(0x7fc00000);
                 st.sp = 0;
                 fhead = 0;
                 fcount = 0;
-                node = pm.n > 1 ? 0 : -1;
-                budget = pm.n;
+                node = r.valid && n > 1 ? 0 : -1;
+                budget = n;
                 slot = idx;
                 has = true;
             }
@@ -263,28 +251,159 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
 
         // finished rays park their T in the wave's pool buffer
         if (has && node < 0 && fcount == 0) {
-            tbuf[wv][slot] = T;
+            tbuf[slot] = T;
             has = false;
         }
     }
     // every lane has left the loop: the pool buffer is complete
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
-    if (lane < nv) {
-        const int64_t m = m0 + lane;
-        const int32_t src = __float_as_int(rec[kLeafF4 * m + 2].w);
+}
+
+// Rays of the all-ray kernel: Gaussians m0 .. m0 + nv - 1 (sorted order) times
+// directions k0 .. k0 + s - 1; pool index idx = j * nv + (m - m0). Origin data
+// come from the prepared per-leaf records.
+struct GridSource {
+    const float4 *rec, *origins;
+    const float *dirs;
+    int64_t m0;
+    int nv, k0, dir_mode;
+    float tmin_scale;
+    __device__ __forceinline__ RaySetup operator()(int idx) const {
+        const int oi = idx % nv, j = idx / nv;
+        const int64_t m = m0 + oi;
+        const float4 r0 = rec[kLeafF4 * m];
+        const float4 og = origins[m];
+        const f3 nrm = mk(og.x, og.y, og.z);
+        f3 b1, b2;
+        onb_duff(nrm, b1, b2);
+        RaySetup r;
+        r.o = mk(r0.x, r0.y, r0.z);
+        r.d = ray_direction(dirs, k0 + j, dir_mode, nrm, b1, b2);
+        r.tmin = tmin_scale * og.w;
+        r.self = __float_as_int(rec[kLeafF4 * m + 2].w);
+        r.self_leaf = (int32_t)m;
+        r.valid = true;
+        return r;
+    }
+};
+
+// Rays given by id r = ids[base + idx] + id_offset = i * K + k. Origin data are
+// recomputed from the input arrays with the same operations as the leaf
+// preparation, so a ray gets the same bits as in the all-ray kernel.
+struct ListSource {
+    const float *mean, *normal, *log_scale, *dirs;
+    int64_t n;
+    int K, dir_mode;
+    float tmin_scale;
+    const int64_t *ids;
+    int64_t id_offset, base;
+    __device__ __forceinline__ RaySetup operator()(int idx) const {
+        RaySetup r;
+        const int64_t rid = ids[base + idx] + id_offset;
+        r.valid = rid >= 0 && rid < n * (int64_t)K;
+        const int64_t i = r.valid ? rid / K : 0;
+        const int k = (int)(rid - i * K);
+        float nx = 0.f, ny = 0.f, nz = 1.f;
+        if (normal) {
+            nx = normal[3 * i]; ny = normal[3 * i + 1]; nz = normal[3 * i + 2];
+            const float nl = sqrtf(nx * nx + ny * ny + nz * nz);
+            nx /= nl; ny /= nl; nz /= nl;
+        }
+        const float smax = expf(fmaxf(log_scale[3 * i], fmaxf(log_scale[3 * i + 1], log_scale[3 * i + 2])));
+        const f3 nrm = mk(nx, ny, nz);
+        f3 b1, b2;
+        onb_duff(nrm, b1, b2);
+        r.o = mk(mean[3 * i], mean[3 * i + 1], mean[3 * i + 2]);
+        r.d = ray_direction(dirs, r.valid ? k : 0, dir_mode, nrm, b1, b2);
+        r.tmin = tmin_scale * smax;
+        r.self = (int32_t)i;
+        r.self_leaf = -1;
+        return r;
+    }
+};
+
+template <bool kCount>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__restrict__ nodes4,
+                                                            const float4 *__restrict__ rec,
+                                                            const float4 *__restrict__ origins,
+                                                            const float *__restrict__ dirs, PoolMap pm, Cuts c,
+                                                            float *__restrict__ vis_ray, double *__restrict__ partial,
+                                                            unsigned long long *__restrict__ totals) {
+    __shared__ int32_t stk[kPoolRing * kTraceBlock];
+    __shared__ int32_t fifo[kFifo * kTraceBlock];
+    __shared__ float tbuf[kWavesPerBlock][kPoolS * 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+    if (w >= pm.n_items) return;  // wave-uniform
+    const int64_t grp = w / pm.n_chunks;
+    const int chunk = (int)(w - grp * pm.n_chunks);
+    GridSource src;
+    src.rec = rec;
+    src.origins = origins;
+    src.dirs = dirs;
+    src.m0 = grp * 64;
+    src.nv = (int)min<int64_t>(64, pm.n - src.m0);
+    src.k0 = chunk * kPoolS;
+    src.dir_mode = c.dir_mode;
+    src.tmin_scale = c.tmin_scale;
+    const int s_eff = min(kPoolS, pm.K - src.k0);
+    int64_t cn = 0, cl = 0, ch = 0;
+    drain_pool<kCount>(nodes4, rec, c, pm.n, src.nv * s_eff, src, stk + threadIdx.x, fifo + threadIdx.x, tbuf[wv],
+                       cn, cl, ch);
+    if (lane < src.nv) {
+        const int64_t m = src.m0 + lane;
+        const int32_t self = __float_as_int(rec[kLeafF4 * m + 2].w);
         double sum = 0.0;
         for (int j = 0; j < s_eff; ++j) {
-            const float t = tbuf[wv][j * nv + lane];
-            if (vis_ray) vis_ray[(int64_t)src * pm.K + k0 + j] = t;
+            const float t = tbuf[wv][j * src.nv + lane];
+            if (vis_ray) vis_ray[(int64_t)self * pm.K + src.k0 + j] = t;
             sum += (double)t;
         }
-        if (partial) partial[(int64_t)chunk * pm.n + src] = sum;
+        if (partial) partial[(int64_t)chunk * pm.n + self] = sum;
     }
     if (kCount) {
         atomicAdd(totals + 0, (unsigned long long)cn);
         atomicAdd(totals + 1, (unsigned long long)cl);
         atomicAdd(totals + 2, (unsigned long long)ch);
+    }
+}
+
+// Listed rays, kPoolS * 64 list entries per wave. The list holds
+// *count entries when count is given (read on the device), else n_list.
+// out_by_value: T goes to out[ids[j]] (the list holds output positions, the
+// ray being id_offset + ids[j]); otherwise to out[j].
+__global__ __launch_bounds__(kTraceBlock) void k_trace_pool_list(
+    const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float *__restrict__ mean,
+    const float *__restrict__ normal, const float *__restrict__ log_scale, int64_t n, const float *__restrict__ dirs,
+    int K, Cuts c, const int64_t *__restrict__ ids, int64_t n_list, const unsigned long long *__restrict__ count,
+    int64_t id_offset, int out_by_value, float *__restrict__ out) {
+    __shared__ int32_t stk[kPoolRing * kTraceBlock];
+    __shared__ int32_t fifo[kFifo * kTraceBlock];
+    __shared__ float tbuf[kWavesPerBlock][kPoolS * 64];
+    constexpr int kPool = kPoolS * 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t total = count ? min<int64_t>(n_list, (int64_t)*count) : n_list;
+    const int64_t base = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * kPool;
+    if (base >= total) return;  // wave-uniform
+    const int pool_n = (int)min<int64_t>(kPool, total - base);
+    ListSource src;
+    src.mean = mean;
+    src.normal = normal;
+    src.log_scale = log_scale;
+    src.dirs = dirs;
+    src.n = n;
+    src.K = K;
+    src.dir_mode = c.dir_mode;
+    src.tmin_scale = c.tmin_scale;
+    src.ids = ids;
+    src.id_offset = id_offset;
+    src.base = base;
+    int64_t cn = 0, cl = 0, ch = 0;
+    drain_pool<false>(nodes4, rec, c, n, pool_n, src, stk + threadIdx.x, fifo + threadIdx.x, tbuf[wv], cn, cl, ch);
+    for (int j = lane; j < pool_n; j += 64) {
+        const int64_t dst = out_by_value ? ids[base + j] : base + j;
+        out[dst] = tbuf[wv][j];
     }
 }
 
@@ -296,49 +415,6 @@ __global__ __launch_bounds__(256) void k_mean_from_partials(const double *__rest
     double s = 0.0;
     for (int c = 0; c < n_chunks; ++c) s += partial[(int64_t)c * n + i];
     vis_mean[i] = (float)(s / (double)K);
-}
-
-// One lane per listed ray; origin data recomputed from the input arrays with
-// the same operations as the leaf preparation, so results match bit for bit.
-__global__ __launch_bounds__(kTraceBlock) void k_trace_list(const float4 *__restrict__ nodes4,
-                                                            const float4 *__restrict__ rec,
-                                                            const float *__restrict__ mean,
-                                                            const float *__restrict__ normal,
-                                                            const float *__restrict__ log_scale, int64_t n,
-                                                            const float *__restrict__ dirs, int K, Cuts c,
-                                                            const int64_t *__restrict__ ids, int64_t n_rays,
-                                                            float *__restrict__ out) {
-    __shared__ int32_t lds[kRing * kTraceBlock];
-    const int64_t s = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
-    if (s >= n_rays) return;
-    const int64_t r = ids[s];
-    if (r < 0 || r >= n * (int64_t)K) {  // not a ray of this scene
-        out[s] = __int_as_float(0x7fc00000);
-        return;
-    }
-    const int64_t i = r / K;
-    const int k = (int)(r - i * K);
-    float nx = 0.f, ny = 0.f, nz = 1.f;
-    if (normal) {
-        nx = normal[3 * i]; ny = normal[3 * i + 1]; nz = normal[3 * i + 2];
-        const float nl = sqrtf(nx * nx + ny * ny + nz * nz);
-        nx /= nl; ny /= nl; nz /= nl;
-    }
-    const float smax = expf(fmaxf(log_scale[3 * i], fmaxf(log_scale[3 * i + 1], log_scale[3 * i + 2])));
-    const f3 nrm = mk(nx, ny, nz);
-    f3 b1, b2;
-    onb_duff(nrm, b1, b2);
-    RayState<kRing> rs;
-    int32_t spill[RingStack<kRing>::kSpill];
-    rs.st.lds = lds + threadIdx.x;
-    rs.st.spill = spill;
-    rs.st.stride = kTraceBlock;
-    NoHit none;
-    rs.start(mk(mean[3 * i], mean[3 * i + 1], mean[3 * i + 2]), ray_direction(dirs, k, c.dir_mode, nrm, b1, b2),
-             c.tmin_scale * smax, (int32_t)i, -1, n);
-    while (rs.node >= 0 && !rs.step(nodes4, rec, c, none)) {
-    }
-    out[s] = rs.T;
 }
 
 // ---- adjoint ----------------------------------------------------------------
@@ -455,6 +531,19 @@ rv_status validate_trace(const char *fn, const void *bvh, const rv_gaussians *g,
 }
 
 }  // namespace
+
+void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs, int K, const Cuts &c,
+                       const int64_t *ids, int64_t n_list, const unsigned long long *count, int64_t id_offset,
+                       bool out_by_value, float *out, hipStream_t stream) {
+    if (n_list <= 0) return;
+    const BvhLayout L = bvh_layout(g->n);
+    const int64_t waves = (n_list + kPoolS * 64 - 1) / (kPoolS * 64);
+    hipLaunchKernelGGL(k_trace_pool_list, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
+                       dim3(kTraceBlock), 0, stream, at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean,
+                       c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, c, ids, n_list, count, id_offset,
+                       out_by_value ? 1 : 0, out);
+}
+
 }  // namespace rv
 
 using namespace rv;
@@ -523,11 +612,7 @@ extern "C" rv_status rv_trace_rays(const void *bvh, const rv_gaussians *g, const
     RV_REQUIRE(n_rays >= 0, RV_ERR_INVALID_ARG, "rv_trace_rays: n_rays < 0");
     if (n_rays == 0) return RV_OK;
     RV_REQUIRE(ray_ids && out, RV_ERR_INVALID_ARG, "rv_trace_rays: null ray_ids or out");
-    const BvhLayout L = bvh_layout(g->n);
-    const Cuts c = make_cuts(*p);
-    hipLaunchKernelGGL(k_trace_list, dim3(grid_for(n_rays, kTraceBlock)), dim3(kTraceBlock), 0, (hipStream_t)stream,
-                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean, p->dir_mode ? g->normal : nullptr,
-                       g->log_scale, g->n, dirs, K, c, ray_ids, n_rays, out);
+    launch_trace_list(bvh, g, dirs, K, make_cuts(*p), ray_ids, n_rays, nullptr, 0, false, out, (hipStream_t)stream);
     return check_launch("rv_trace_rays");
 }
 

@@ -294,4 +294,13 @@ struct RayState {
     }
 };
 
+// Enqueue the pooled traversal of listed rays on `stream` (defined with the
+// traversal kernels): ray j is ids[j] + id_offset = i * K + k; its T goes to
+// out[ids[j]] (out_by_value) or out[j]. With count non-null, only the first
+// min(n_list, *count) entries (read on the device) are traced. Ids outside
+// [0, n K) give NaN.
+void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs, int K, const Cuts &c,
+                       const int64_t *ids, int64_t n_list, const unsigned long long *count, int64_t id_offset,
+                       bool out_by_value, float *out, hipStream_t stream);
+
 }  // namespace rv
