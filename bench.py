@@ -53,12 +53,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="object", choices=["object", "multi", "tiny"])
+    ap.add_argument("--workload", default="object", choices=["object", "multi", "tiny", "surrogate"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy probe (known-size reference for counters)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--sur-train-samples", type=int, default=8_000_000)
     ap.add_argument("--sur-steps", type=int, default=2000)
     ap.add_argument("--sur-batch", type=int, default=16384)
@@ -81,9 +82,10 @@ def surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, plain_rays_per_s):
     R = n * K
     T_all = vis_ray.reshape(-1)
     gen = torch.Generator(device="cpu").manual_seed(2311)
-    perm = torch.randperm(R, generator=gen)
-    tr_ids = perm[: args.sur_train_samples].to(dev)
-    ho_ids = perm[-1_000_000:].to(dev)
+    # uniform draws (a permutation of all R ids would not fit the host at the largest workload);
+    # the chance that a held-out id is also a training id is train_samples / R
+    tr_ids = torch.randint(R, (min(args.sur_train_samples, R),), generator=gen).to(dev)
+    ho_ids = torch.randint(R, (min(1_000_000, R),), generator=gen).to(dev)
     o, d = ray_setup(g, dirs, tr_ids, prm)
     T_tr = T_all[tr_ids]
     lo = g.mean.min(0).values.cpu().tolist()
@@ -140,6 +142,44 @@ def surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, plain_rays_per_s):
     )
 
 
+def adjoint_leg(torch, dev):
+    """Forward and adjoint on the differentiation workload (200,000 Gaussians x
+    128 hemisphere directions) with the loss L = mean_i (Vbar_i - y_i)^2: the
+    upstream gradient is dL/dVbar_i = 2 (Vbar_i - y_i) / n. Times the adjoint
+    with the forward's saved transmittances (one traversal per ray) and without
+    (it re-traces to recover them)."""
+    from paper_2311_16043_amd import Gaussians, TraceParams, build_bvh, trace_visibility, trace_visibility_backward
+    from workloads import scenes
+    sc = scenes.make_scene("diff")
+    g = Gaussians.from_scene(sc, device=dev)
+    dirs = torch.from_numpy(scenes.preset_dirs("diff")).to(dev)
+    prm = TraceParams(dir_mode=scenes.PRESETS["diff"]["dir_mode"])
+    bvh = build_bvh(g)
+    y = torch.from_numpy(np.random.Generator(np.random.PCG64(16043 + 3)).uniform(0, 1, g.n).astype(np.float32)).to(dev)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), r
+
+    fwd_ms, (vr, vm) = timed(lambda: trace_visibility(bvh, g, dirs, prm))
+    gmean = 2.0 * (vm - y) / g.n
+    bwd_ms, _ = timed(lambda: trace_visibility_backward(bvh, g, dirs, prm, grad_vis_mean=gmean, vis_ray_fwd=vr))
+    bwd2_ms, _ = timed(lambda: trace_visibility_backward(bvh, g, dirs, prm, grad_vis_mean=gmean))
+    rays = g.n * int(dirs.shape[0])
+    return dict(workload="differentiation: 200,000 object-scale Gaussians x 128 hemisphere directions",
+                rays=rays, forward_ms=fwd_ms, backward_ms=bwd_ms, backward_rays_per_s=rays / (bwd_ms / 1000.0),
+                backward_retrace_ms=bwd2_ms, backward_over_forward=bwd_ms / fwd_ms)
+
+
 def copy_probe(torch, nbytes=1 << 31, iters=5):
     """Achievable HBM bandwidth of the library's streaming copy: read + write bytes / time."""
     from paper_2311_16043_amd import stream_copy
@@ -165,7 +205,7 @@ def cpu_baseline(scene, dirs, dir_mode, target_s):
     t = time.perf_counter()
     oracle.trace_rays(scene, dirs, dir_mode, scenes.sample_ray_ids(n, K, 1, seed=98))
     setup = time.perf_counter() - t
-    pilot = scenes.sample_ray_ids(n, K, 512, seed=99)
+    pilot = scenes.sample_ray_ids(n, K, max(16, min(512, 512 * 300_000 // n)), seed=99)
     t = time.perf_counter()
     oracle.trace_rays(scene, dirs, dir_mode, pilot)
     per_ray = max(time.perf_counter() - t - setup, 1e-3) / pilot.size
@@ -266,7 +306,9 @@ def main():
             "workload": {"object": "object-scale: unit sphere on a 4x4 plane, 300,000 surface Gaussians x 256 "
                                    "hemisphere directions",
                          "multi": "multi-object: 8 objects x 150,000 surface Gaussians x 512 hemisphere directions",
-                         "tiny": "tiny: 2,000 Gaussians x 64 sphere directions"}[name],
+                         "tiny": "tiny: 2,000 Gaussians x 64 sphere directions",
+                         "surrogate": "surrogate-scale: 20 objects x 150,000 surface Gaussians x 1,024 hemisphere "
+                                      "directions"}[name],
             "n_gaussians": n, "directions": K, "rays_per_step": rays,
             "step": "build_bvh + trace_visibility (vis_ray and vis_mean)",
         },
@@ -293,6 +335,9 @@ def main():
     if not args.no_surrogate and name != "tiny":
         out["surrogate"] = surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, rays / trace_s)
         print(f"[bench] surrogate: {json.dumps(out['surrogate'])}", file=sys.stderr, flush=True)
+    if not args.no_adjoint and name == "object":
+        out["adjoint"] = adjoint_leg(torch, dev)
+        print(f"[bench] adjoint: {json.dumps(out['adjoint'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, dirs_np, dir_mode, args.cpu_seconds)
     print(json.dumps(out), flush=True)

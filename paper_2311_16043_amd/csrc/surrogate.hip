@@ -110,7 +110,8 @@ struct FwdArgs {
     const float *master;
     const u32x4 *fwd;
     const float *header;
-    int64_t n;               // samples (queries) in this launch
+    int64_t n;               // samples (queries) in all launches of this call
+    int64_t s_off;           // first sample of this launch (a grid covers at most 2^30 samples)
     // explicit inputs (xd and train)
     const float *x, *d, *T;
     // training: sample draw and saved tensors
@@ -210,7 +211,7 @@ __device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
     constexpr int NT = 2;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t s_base = wave * (16 * NT);
+    const int64_t s_base = a.s_off + wave * (16 * NT);
     if (s_base >= a.n) return;  // wave-uniform
     const int g = lane >> 4, col = lane & 15;
     const float lo0 = a.header[0], lo1 = a.header[1], lo2 = a.header[2];
@@ -674,6 +675,9 @@ inline TrainWs train_ws(int64_t batch) {
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+// Samples per inference launch: a dispatch counts its work-items in 32 bits,
+// so one grid stays at 2^30 samples (2^23 blocks of 256).
+constexpr int64_t kLaunchSamples = int64_t(1) << 30;
 
 // forward (train) + backward + weight gradients + reduction on samples [0, n)
 rv_status loss_grad_impl(const void *params, const float *x, const float *d, const float *T, int64_t n, bool hashed,
@@ -840,8 +844,12 @@ extern "C" rv_status rv_surrogate_infer_xd(const void *params, const float *x, c
     fa.d = d;
     fa.vis = vis;
     fa.unc = unc;
-    hipLaunchKernelGGL(k_mlp_forward<kModeXd>, dim3(blocks_for((n + 31) / 32, 4)), dim3(256), 0, (hipStream_t)stream,
-                       fa);
+    for (int64_t off = 0; off < n; off += kLaunchSamples) {
+        fa.s_off = off;
+        const int64_t cnt = std::min(kLaunchSamples, n - off);
+        hipLaunchKernelGGL(k_mlp_forward<kModeXd>, dim3(blocks_for((cnt + 31) / 32, 4)), dim3(256), 0,
+                           (hipStream_t)stream, fa);
+    }
     return check_launch("rv_surrogate_infer_xd");
 }
 
@@ -884,7 +892,11 @@ extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, con
     fa.tau = tau;
     fa.fb_list = bvh ? list : nullptr;
     fa.fb_count = count;
-    hipLaunchKernelGGL(k_mlp_forward<kModeGrid>, dim3(blocks_for((q_count + 31) / 32, 4)), dim3(256), 0, s, fa);
+    for (int64_t off = 0; off < q_count; off += kLaunchSamples) {
+        fa.s_off = off;
+        const int64_t cnt = std::min(kLaunchSamples, q_count - off);
+        hipLaunchKernelGGL(k_mlp_forward<kModeGrid>, dim3(blocks_for((cnt + 31) / 32, 4)), dim3(256), 0, s, fa);
+    }
     if (bvh) {
         const Cuts c = make_cuts(*p);
         // the compacted fallback list holds positions s; the ray is q_begin + s

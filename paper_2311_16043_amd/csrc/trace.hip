@@ -108,7 +108,12 @@ struct PoolMap {
     int K, n_chunks;
     int64_t n_items;   // ceil(n / 64) * n_chunks
     int64_t n_blocks;
+    int64_t w_off;     // first wave of this launch
 };
+
+// Waves per launch: a dispatch counts its work-items in 32 bits, so one grid
+// stays at 2^24 waves (2^30 work-items).
+constexpr int64_t kLaunchWaves = int64_t(1) << 24;
 
 inline PoolMap make_pool(int64_t n, int K) {
     PoolMap pm;
@@ -117,6 +122,7 @@ inline PoolMap make_pool(int64_t n, int K) {
     pm.n_chunks = (K + kPoolS - 1) / kPoolS;
     pm.n_items = ((n + 63) / 64) * (int64_t)pm.n_chunks;
     pm.n_blocks = (pm.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
+    pm.w_off = 0;
     return pm;
 }
 
@@ -334,7 +340,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
     __shared__ int32_t fifo[kFifo * kTraceBlock];
     __shared__ float tbuf[kWavesPerBlock][kPoolS * 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+    const int64_t w = pm.w_off + xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
     if (w >= pm.n_items) return;  // wave-uniform
     const int64_t grp = w / pm.n_chunks;
     const int chunk = (int)(w - grp * pm.n_chunks);
@@ -573,9 +579,14 @@ extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g,
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_trace_pool<false>, dim3((unsigned)pm.n_blocks), dim3(kTraceBlock), 0, s,
-                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, pm, c,
-                       vis_ray, partial, (unsigned long long *)nullptr);
+    for (int64_t w0 = 0; w0 < pm.n_items; w0 += kLaunchWaves) {
+        PoolMap part = pm;
+        part.w_off = w0;
+        const int64_t nb = (std::min(kLaunchWaves, pm.n_items - w0) + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL(k_trace_pool<false>, dim3((unsigned)nb), dim3(kTraceBlock), 0, s, at<float4>(bvh, L.nodes4),
+                           at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, part, c, vis_ray, partial,
+                           (unsigned long long *)nullptr);
+    }
     if (vis_mean)
         hipLaunchKernelGGL(k_mean_from_partials, dim3(grid_for(g->n, 256)), dim3(256), 0, s, partial, g->n,
                            pm.n_chunks, K, vis_mean);
@@ -597,9 +608,14 @@ extern "C" rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, cons
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(totals), (int64_t)6,
                        0u);
-    hipLaunchKernelGGL(k_trace_pool<true>, dim3((unsigned)pm.n_blocks), dim3(kTraceBlock), 0, s,
-                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, pm, c,
-                       (float *)nullptr, (double *)nullptr, (unsigned long long *)totals);
+    for (int64_t w0 = 0; w0 < pm.n_items; w0 += kLaunchWaves) {
+        PoolMap part = pm;
+        part.w_off = w0;
+        const int64_t nb = (std::min(kLaunchWaves, pm.n_items - w0) + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL(k_trace_pool<true>, dim3((unsigned)nb), dim3(kTraceBlock), 0, s, at<float4>(bvh, L.nodes4),
+                           at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, part, c, (float *)nullptr,
+                           (double *)nullptr, (unsigned long long *)totals);
+    }
     return check_launch("rv_trace_stats");
 }
 
