@@ -3,16 +3,16 @@
 // per-Gaussian average over the K directions (the "averaged visibility" of the
 // ablation study, Sec. 5.4).
 //
-// Work mapping. The forward kernel gives each wave 64 Gaussians adjacent in
-// Morton (sorted-leaf) order and a chunk of consecutive directions, a pool of
-// rays that its lanes drain (see the pooled traversal below). The adjoint
-// gives each lane one Gaussian's chunk of S directions, traced one after the
-// other. Either way ~16M lanes' worth of work items let the hardware
-// dispatcher balance the skewed per-ray work across many waves instead of
-// waiting on the slowest Gaussian. Blocks are renumbered so that each XCD
-// (round-robin dispatch) walks a contiguous range of the Morton order and its
-// L2 sees a compact part of the tree. Per-Gaussian sums are FP64 partials per
-// chunk, added in chunk order by a second kernel (deterministic, no atomics).
+// Work mapping. Every kernel drains pools of rays with the lanes of a wave
+// (see the pooled traversal below): the all-ray forward and the adjoint take
+// 64 Gaussians adjacent in Morton (sorted-leaf) order times a chunk of 4
+// consecutive directions per wave, the list kernel 256 consecutive list
+// entries. ~300k small pools at object scale let the hardware dispatcher
+// balance the skewed per-ray work instead of waiting on the slowest Gaussian.
+// Blocks are renumbered so that each XCD (round-robin dispatch) walks a
+// contiguous range of the Morton order and its L2 sees a compact part of the
+// tree. Per-Gaussian sums are FP64 partials per chunk, added in chunk order by
+// a second kernel (deterministic, no atomics).
 #include "trace_core.h"
 
 namespace rv {
@@ -20,50 +20,7 @@ namespace {
 
 constexpr int kTraceBlock = 256;
 constexpr int kWavesPerBlock = kTraceBlock / 64;
-constexpr int kRing = 16;
-constexpr int64_t kTargetLanes = 16 << 20;
 constexpr int kXcds = 8;
-
-struct Origin {
-    f3 o, nrm, b1, b2;
-    float tmin;
-    int32_t src;
-};
-
-__device__ __forceinline__ Origin load_origin(const float4 *__restrict__ rec, const float4 *__restrict__ origins,
-                                              int64_t m, const Cuts &c) {
-    Origin g;
-    const float4 r0 = rec[kLeafF4 * m];
-    const float4 og = origins[m];
-    g.src = __float_as_int(rec[kLeafF4 * m + 2].w);
-    g.o = mk(r0.x, r0.y, r0.z);
-    g.nrm = mk(og.x, og.y, og.z);
-    g.tmin = c.tmin_scale * og.w;
-    onb_duff(g.nrm, g.b1, g.b2);
-    return g;
-}
-
-// Chunking of the n*K rays: n_chunks chunks of S directions per Gaussian.
-struct ChunkMap {
-    int64_t n;
-    int K, S, n_chunks;
-    int64_t n_items;   // waves of work: ceil(n / 64) * n_chunks
-    int64_t n_blocks;
-};
-
-inline ChunkMap make_chunks(int64_t n, int K) {
-    ChunkMap cm;
-    cm.n = n;
-    cm.K = K;
-    int64_t want = (kTargetLanes + n - 1) / n;
-    if (want < 1) want = 1;
-    if (want > K) want = K;
-    cm.S = (int)((K + want - 1) / want);
-    cm.n_chunks = (K + cm.S - 1) / cm.S;
-    cm.n_items = ((n + 63) / 64) * (int64_t)cm.n_chunks;
-    cm.n_blocks = (cm.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
-    return cm;
-}
 
 // Renumber blocks so that the blocks dispatched to XCD x (b % 8 == x) form a
 // contiguous range of logical blocks. A bijection on [0, nb).
@@ -71,20 +28,6 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
     const int64_t q = nb / kXcds, r = nb % kXcds;
     const int64_t x = b % kXcds;
     return x * q + (x < r ? x : r) + b / kXcds;
-}
-
-// This lane's Gaussian (sorted position m), chunk and direction range.
-__device__ __forceinline__ bool lane_work(const ChunkMap &cm, int64_t &m, int &chunk, int &k0, int &k1) {
-    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t w = b * kWavesPerBlock + threadIdx.x / 64;
-    if (w >= cm.n_items) return false;
-    const int64_t grp = w / cm.n_chunks;
-    chunk = (int)(w - grp * cm.n_chunks);
-    m = grp * 64 + (threadIdx.x & 63);
-    if (m >= cm.n) return false;
-    k0 = chunk * cm.S;
-    k1 = min(cm.K, k0 + cm.S);
-    return true;
 }
 
 // ---- pooled traversal -----------------------------------------------------------
@@ -97,7 +40,8 @@ __device__ __forceinline__ bool lane_work(const ChunkMap &cm, int64_t &m, int &c
 // pending leaf once enough of them have one, so the expensive exact test
 // executes with most lanes active instead of inside every node step. Leaves
 // are tested in discovery (FIFO) order, so each ray's product, and its early
-// exit, is the same as a single-ray traversal's, bit for bit.
+// exit, do not depend on which pool the ray was drained from: the all-ray,
+// ray-list and adjoint kernels give a ray the same bits.
 constexpr int kPoolS = 4;
 constexpr int kFifo = 8;
 constexpr int kPoolRing = 8;
@@ -124,6 +68,64 @@ inline PoolMap make_pool(int64_t n, int K) {
     pm.n_blocks = (pm.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
     pm.w_off = 0;
     return pm;
+}
+
+// One node visit of a pooled ray: hit leaves are appended to the lane's FIFO
+// (slot order), the first hit internal child becomes the next node and the
+// others are stacked to come off in slot order. A malformed tree (visit
+// budget spent, stack full) ends the ray with NaN.
+template <bool kCount>
+__device__ __forceinline__ void pool_node_step(const float4 *__restrict__ nodes4, f3 o, f3 inv, float tmin,
+                                               int32_t &node, int64_t &budget, RingStack<kPoolRing> &st,
+                                               int32_t *my_fifo, int fhead, int &fcount, float &T, int64_t &cn) {
+    if (--budget < 0) {
+        node = -1;
+        fcount = 0;
+        T = __int_as_float(0x7fc00000);
+        return;
+    }
+    int32_t id[4];
+    visit4(nodes4, node, o, inv, tmin, id);
+    if (kCount) ++cn;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (is_leaf(id[s])) {
+            my_fifo[((fhead + fcount) & (kFifo - 1)) * kTraceBlock] = ~id[s];
+            ++fcount;
+        }
+    }
+    int32_t nxt = -1;
+    bool overflow = false;
+#pragma unroll
+    for (int s = 3; s >= 0; --s) {
+        if (id[s] >= 0) {
+            if (nxt >= 0) {
+                if (st.full()) overflow = true;
+                else st.push(nxt);
+            }
+            nxt = id[s];
+        }
+    }
+    if (overflow) {
+        node = -1;
+        fcount = 0;
+        T = __int_as_float(0x7fc00000);
+    } else if (nxt >= 0) {
+        node = nxt;
+    } else if (!st.empty()) {
+        node = st.pop();
+    } else {
+        node = -1;
+    }
+}
+
+// Wave-level leaf phase condition: enough lanes hold a pending leaf, or some
+// lane cannot walk for lack of FIFO room, or no lane can walk.
+__device__ __forceinline__ bool leaf_phase_now(bool has, int32_t node, int fcount) {
+    const uint64_t pend = __ballot(has && fcount > 0);
+    const uint64_t blocked = __ballot(has && fcount > kFifo - 4);
+    const uint64_t trav = __ballot(has && node >= 0 && fcount <= kFifo - 4);
+    return pend != 0 && (__popcll(pend) >= kLeafMin || blocked != 0 || trav == 0);
 }
 
 // One ray as a pool source hands it out.
@@ -189,55 +191,12 @@ __device__ __forceinline__ void drain_pool(const float4 *__restrict__ nodes4, co
 
         // node phase: one four-wide node per lane with traversal work and FIFO
         // room for all four children
-        const bool can_node = has && node >= 0 && fcount <= kFifo - 4;
-        if (can_node) {
-            if (--budget < 0) {
-                node = -1;
-                fcount = 0;
-                T = __int_as_float(0x7fc00000);
-            } else {
-                int32_t id[4];
-                visit4(nodes4, node, o, inv, tmin, id);
-                if (kCount) ++cn;
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    if (is_leaf(id[s])) {
-                        my_fifo[((fhead + fcount) & (kFifo - 1)) * kTraceBlock] = ~id[s];
-                        ++fcount;
-                    }
-                }
-                int32_t nxt = -1;
-                bool overflow = false;
-#pragma unroll
-                for (int s = 3; s >= 0; --s) {
-                    if (id[s] >= 0) {
-                        if (nxt >= 0) {
-                            if (st.full()) overflow = true;
-                            else st.push(nxt);
-                        }
-                        nxt = id[s];
-                    }
-                }
-                if (overflow) {
-                    node = -1;
-                    fcount = 0;
-                    T = __int_as_float(0x7fc00000);
-                } else if (nxt >= 0) {
-                    node = nxt;
-                } else if (!st.empty()) {
-                    node = st.pop();
-                } else {
-                    node = -1;
-                }
-            }
-        }
+        if (has && node >= 0 && fcount <= kFifo - 4)
+            pool_node_step<kCount>(nodes4, o, inv, tmin, node, budget, st, my_fifo, fhead, fcount, T, cn);
 
         // leaf phase: test one pending leaf per lane when enough lanes have one,
         // when a lane cannot traverse for lack of FIFO room, or when no lane can traverse
-        const uint64_t pend = __ballot(has && fcount > 0);
-        const uint64_t blocked = __ballot(has && fcount > kFifo - 4);
-        const uint64_t trav = __ballot(has && node >= 0 && fcount <= kFifo - 4);
-        if (pend != 0 && (__popcll(pend) >= kLeafMin || blocked != 0 || trav == 0)) {
+        if (leaf_phase_now(has, node, fcount)) {
             if (has && fcount > 0) {
                 const int32_t leaf = my_fifo[fhead * kTraceBlock];
                 fhead = (fhead + 1) & (kFifo - 1);
@@ -425,90 +384,226 @@ __global__ __launch_bounds__(256) void k_mean_from_partials(const double *__rest
 
 // ---- adjoint ----------------------------------------------------------------
 
+// Per-block accumulation table of the scatter: the four waves of a block
+// trace 64 adjacent origins x 16 directions, whose hits concentrate on the
+// same nearby Gaussians, so their seven sums are added in LDS and flushed
+// with one set of global atomics per Gaussian at the end of the block.
+constexpr int kHashSlots = 1024;
+constexpr int kHashProbes = 8;
+
+struct GradTable {
+    int32_t key[kHashSlots];         // Gaussian index, -1 when free
+    float val[7][kHashSlots];        // opacity, mean xyz, log-scale xyz
+
+    // Slot of Gaussian j (claimed if free), or -1 after kHashProbes probes.
+    __device__ __forceinline__ int find(int32_t j) {
+        const uint32_t h = ((uint32_t)j * 2654435761u) >> 22;   // 10 bits
+#pragma unroll
+        for (int p = 0; p < kHashProbes; ++p) {
+            const int s = (int)((h + p) & (kHashSlots - 1));
+            const int32_t k = atomicCAS(&key[s], -1, j);
+            if (k == -1 || k == j) return s;
+        }
+        return -1;
+    }
+};
+
 struct GradScatter {
+    bool active;        // false on the pass that only recovers T_final
     float g_over;       // -(dL/dT) * T_final for the current ray
     float *go, *gm, *gl;
-    f3 origin;          // accumulated d/d(origin), flushed once per Gaussian
+    GradTable *table;
+    f3 origin;          // accumulated d/d(origin) of the current ray
 
     __device__ __forceinline__ void operator()(const LeafHit &h, float) {
-        if (h.clamped) return;
+        if (!active || h.clamped) return;
         const float ga = g_over / h.one_minus;   // dL/dalpha
         const float a = ga * h.alpha;
         const f3 wte = h.e.x * h.w0 + h.e.y * h.w1 + h.e.z * h.w2;   // W^T e
-        const int64_t j = h.src;
-        unsafeAtomicAdd(go + j, a / h.opacity);
-        unsafeAtomicAdd(gm + 3 * j + 0, a * wte.x);
-        unsafeAtomicAdd(gm + 3 * j + 1, a * wte.y);
-        unsafeAtomicAdd(gm + 3 * j + 2, a * wte.z);
-        unsafeAtomicAdd(gl + 3 * j + 0, a * h.e.x * h.e.x);
-        unsafeAtomicAdd(gl + 3 * j + 1, a * h.e.y * h.e.y);
-        unsafeAtomicAdd(gl + 3 * j + 2, a * h.e.z * h.e.z);
+        const float v[7] = {a / h.opacity, a * wte.x, a * wte.y, a * wte.z,
+                            a * h.e.x * h.e.x, a * h.e.y * h.e.y, a * h.e.z * h.e.z};
+        const int slot = table->find(h.src);
+        if (slot >= 0) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) atomicAdd(&table->val[c][slot], v[c]);
+        } else {
+            const int64_t j = h.src;
+            unsafeAtomicAdd(go + j, v[0]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                unsafeAtomicAdd(gm + 3 * j + c, v[1 + c]);
+                unsafeAtomicAdd(gl + 3 * j + c, v[4 + c]);
+            }
+        }
         origin = origin - a * wte;
     }
 };
 
+// Adjoint over the same pools as the forward (64 Gaussians x a chunk of
+// directions per wave). Each ray with a nonzero upstream gradient
+// g = dL/dV_ik (grad_ray) + dL/dVbar_i / K (grad_mean) is traced once to
+// recover T_final (skipped when the forward's T are given), then again with
+// the same visits in the same order, scattering dL/dalpha_j = -g T_final /
+// (1 - alpha_j) into each included, unclamped Gaussian's parameters (through
+// the block's LDS table). The source's own term (through the ray origin) is
+// summed per Gaussian in LDS and added once per wave.
 __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float4 *__restrict__ origins,
-    const float *__restrict__ dirs, ChunkMap cm, Cuts c, const float *__restrict__ grad_ray,
+    const float *__restrict__ dirs, PoolMap pm, Cuts c, const float *__restrict__ grad_ray,
     const float *__restrict__ grad_mean_in, const float *__restrict__ vis_fwd, float *go, float *gm, float *gl) {
-    __shared__ int32_t lds[kRing * kTraceBlock];
-    int64_t m;
-    int chunk, k0, k1;
-    if (!lane_work(cm, m, chunk, k0, k1)) return;
-    const int K = cm.K;
-    const Origin g = load_origin(rec, origins, m, c);
-    RayState<kRing> rs;
-    int32_t spill[RingStack<kRing>::kSpill];
-    rs.st.lds = lds + threadIdx.x;
-    rs.st.spill = spill;
-    rs.st.stride = kTraceBlock;
-    NoHit none;
+    __shared__ int32_t stk[kPoolRing * kTraceBlock];
+    __shared__ int32_t fifo[kFifo * kTraceBlock];
+    __shared__ float ogr[kWavesPerBlock][64 * 3];
+    __shared__ GradTable table;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int s = threadIdx.x; s < kHashSlots; s += kTraceBlock) {
+        table.key[s] = -1;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) table.val[c][s] = 0.0f;
+    }
+    __syncthreads();
+    // every wave reaches the final barrier; waves past the end trace nothing
+    int64_t w = pm.w_off + xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+    const bool wave_live = w < pm.n_items;
+    if (!wave_live) w = 0;
+    const int64_t grp = w / pm.n_chunks;
+    const int chunk = (int)(w - grp * pm.n_chunks);
+    GridSource src;
+    src.rec = rec;
+    src.origins = origins;
+    src.dirs = dirs;
+    src.m0 = grp * 64;
+    src.nv = (int)min<int64_t>(64, pm.n - src.m0);
+    src.k0 = chunk * kPoolS;
+    src.dir_mode = c.dir_mode;
+    src.tmin_scale = c.tmin_scale;
+    const int pool_n = wave_live ? src.nv * min(kPoolS, pm.K - src.k0) : 0;
+    const int K = pm.K;
+    ogr[wv][lane] = 0.f;
+    ogr[wv][64 + lane] = 0.f;
+    ogr[wv][128 + lane] = 0.f;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+
+    const uint64_t lt = (1ull << lane) - 1ull;
+    RingStack<kPoolRing> st;
+    int32_t spill[RingStack<kPoolRing>::kSpill];
+    st.lds = stk + threadIdx.x;
+    st.spill = spill;
+    st.stride = kTraceBlock;
+    st.sp = 0;
+    int32_t *my_fifo = fifo + threadIdx.x;
+    int fhead = 0, fcount = 0;
+    bool has = false;
+    int oi = 0;        // pool origin of the current ray
+    float gk = 0.f;    // upstream gradient of the current ray
+    f3 o = mk(0.f, 0.f, 0.f), d = o, inv = o;
+    float tmin = 0.f, T = 1.f;
+    int32_t self = -1, self_leaf = -1, node = -1;
+    int64_t budget = 0;
+    int64_t cn = 0;
     GradScatter gs;
+    gs.active = false;
+    gs.g_over = 0.f;
     gs.go = go;
     gs.gm = gm;
     gs.gl = gl;
+    gs.table = &table;
     gs.origin = mk(0.f, 0.f, 0.f);
-    const float gmean = grad_mean_in ? grad_mean_in[g.src] / (float)K : 0.0f;
-    int k = k0;
-    int phase = 0;
-    float gk = 0.0f;
-    // next ray of this lane's chunk with a nonzero upstream gradient
-    auto begin_ray = [&](int kk) -> bool {
-        for (; kk < k1; ++kk) {
-            gk = gmean + (grad_ray ? grad_ray[(int64_t)g.src * K + kk] : 0.0f);
-            if (gk != 0.0f) break;
-        }
-        k = kk;
-        if (k >= k1) return false;
-        rs.start(g.o, ray_direction(dirs, k, c.dir_mode, g.nrm, g.b1, g.b2), g.tmin, g.src, (int32_t)m, cm.n);
-        if (vis_fwd) {
-            phase = 1;
-            gs.g_over = -gk * vis_fwd[(int64_t)g.src * K + k];
-        } else {
-            phase = 0;
-        }
-        return true;
+    int next = 0;  // wave-uniform
+    auto restart = [&]() {
+        T = 1.0f;
+        st.sp = 0;
+        fhead = 0;
+        fcount = 0;
+        node = pm.n > 1 ? 0 : -1;
+        budget = pm.n;
     };
-    bool live = begin_ray(k0);
-    while (live) {
-        bool done;
-        if (phase == 0) {
-            // first pass: the ray's final T (same traversal, same early exit)
-            done = rs.node < 0 || rs.step(nodes4, rec, c, none);
-            if (done) {
-                gs.g_over = -gk * rs.T;
-                rs.start(rs.o, rs.d, rs.tmin, rs.self, rs.self_leaf, cm.n);
-                phase = 1;
+
+    while (true) {
+        const uint64_t need = __ballot(!has);
+        if (need != 0 && next < pool_n) {
+            const int idx = next + __popcll(need & lt);
+            if (!has && idx < pool_n) {
+                const RaySetup r = src(idx);
+                oi = idx % src.nv;
+                const int k = src.k0 + idx / src.nv;
+                gk = (grad_mean_in ? grad_mean_in[r.self] / (float)K : 0.0f) +
+                     (grad_ray ? grad_ray[(int64_t)r.self * K + k] : 0.0f);
+                o = r.o;
+                d = r.d;
+                inv = safe_inv(d);
+                tmin = r.tmin;
+                self = r.self;
+                self_leaf = r.self_leaf;
+                restart();
+                gs.origin = mk(0.f, 0.f, 0.f);
+                gs.active = vis_fwd != nullptr;
+                gs.g_over = vis_fwd ? -gk * vis_fwd[(int64_t)r.self * K + k] : 0.0f;
+                if (gk == 0.0f) {   // nothing to propagate: the ray ends here
+                    node = -1;
+                    gs.active = true;
+                }
+                has = true;
             }
-        } else {
-            done = rs.node < 0 || rs.step(nodes4, rec, c, gs);
-            if (done) live = begin_ray(k + 1);
+            next += __popcll(need);
+        }
+        if (__ballot(has) == 0) break;
+
+        if (has && node >= 0 && fcount <= kFifo - 4)
+            pool_node_step<false>(nodes4, o, inv, tmin, node, budget, st, my_fifo, fhead, fcount, T, cn);
+
+        if (leaf_phase_now(has, node, fcount)) {
+            if (has && fcount > 0) {
+                const int32_t leaf = my_fifo[fhead * kTraceBlock];
+                fhead = (fhead + 1) & (kFifo - 1);
+                --fcount;
+                T *= leaf_factor(rec, leaf, o, d, tmin, self, self_leaf, c, gs, T);
+                if (T < c.T_stop) {
+                    node = -1;
+                    fcount = 0;
+                }
+            }
+        }
+
+        if (has && node < 0 && fcount == 0) {
+            if (!gs.active) {
+                // T_final is known: trace the same ray again, scattering
+                gs.g_over = -gk * T;
+                gs.active = true;
+                restart();
+            } else {
+                if (gs.origin.x != 0.f || gs.origin.y != 0.f || gs.origin.z != 0.f) {
+                    atomicAdd(&ogr[wv][3 * oi + 0], gs.origin.x);
+                    atomicAdd(&ogr[wv][3 * oi + 1], gs.origin.y);
+                    atomicAdd(&ogr[wv][3 * oi + 2], gs.origin.z);
+                }
+                has = false;
+            }
         }
     }
-    if (gs.origin.x != 0.f || gs.origin.y != 0.f || gs.origin.z != 0.f) {
-        unsafeAtomicAdd(gm + 3 * (int64_t)g.src + 0, gs.origin.x);
-        unsafeAtomicAdd(gm + 3 * (int64_t)g.src + 1, gs.origin.y);
-        unsafeAtomicAdd(gm + 3 * (int64_t)g.src + 2, gs.origin.z);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (wave_live && lane < src.nv) {
+        const float ox = ogr[wv][3 * lane], oy = ogr[wv][3 * lane + 1], oz = ogr[wv][3 * lane + 2];
+        if (ox != 0.f || oy != 0.f || oz != 0.f) {
+            const int64_t j = __float_as_int(rec[kLeafF4 * (src.m0 + lane) + 2].w);
+            unsafeAtomicAdd(gm + 3 * j + 0, ox);
+            unsafeAtomicAdd(gm + 3 * j + 1, oy);
+            unsafeAtomicAdd(gm + 3 * j + 2, oz);
+        }
+    }
+    // the block's table: one set of global atomics per Gaussian
+    __syncthreads();
+    for (int s = threadIdx.x; s < kHashSlots; s += kTraceBlock) {
+        const int64_t j = table.key[s];
+        if (j < 0) continue;
+        unsafeAtomicAdd(go + j, table.val[0][s]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            unsafeAtomicAdd(gm + 3 * j + c, table.val[1 + c][s]);
+            unsafeAtomicAdd(gl + 3 * j + c, table.val[4 + c][s]);
+        }
     }
 }
 
@@ -644,11 +739,16 @@ extern "C" rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaus
                "rv_trace_visibility_backward: both upstream gradients are NULL");
     RV_REQUIRE(grad_opacity && grad_mean && grad_log_scale, RV_ERR_INVALID_ARG,
                "rv_trace_visibility_backward: null gradient output");
-    const ChunkMap cm = make_chunks(g->n, K);
+    const PoolMap pm = make_pool(g->n, K);
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
-    hipLaunchKernelGGL(k_trace_backward, dim3((unsigned)cm.n_blocks), dim3(kTraceBlock), 0, (hipStream_t)stream,
-                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, cm, c,
-                       grad_vis_ray, grad_vis_mean, vis_ray_fwd, grad_opacity, grad_mean, grad_log_scale);
+    for (int64_t w0 = 0; w0 < pm.n_items; w0 += kLaunchWaves) {
+        PoolMap part = pm;
+        part.w_off = w0;
+        const int64_t nb = (std::min(kLaunchWaves, pm.n_items - w0) + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL(k_trace_backward, dim3((unsigned)nb), dim3(kTraceBlock), 0, (hipStream_t)stream,
+                           at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs,
+                           part, c, grad_vis_ray, grad_vis_mean, vis_ray_fwd, grad_opacity, grad_mean, grad_log_scale);
+    }
     return check_launch("rv_trace_visibility_backward");
 }

@@ -215,85 +215,6 @@ struct RingStack {
     }
 };
 
-// One ray's traversal state; step() processes one four-wide node.
-template <int kRing>
-struct RayState {
-    f3 o, d, inv;   // origin, unit direction, 1/d
-    float tmin, T;
-    int32_t self;       // original index of the source Gaussian
-    int32_t self_leaf;  // its sorted leaf position, or -1 if unknown
-    int32_t node;   // next internal node to visit, -1 when finished
-    int64_t budget; // steps left: a ray visits each of the n-1 internal nodes at most once
-    RingStack<kRing> st;
-
-    __device__ __forceinline__ void start(f3 o_, f3 d_, float tmin_, int32_t self_, int32_t self_leaf_, int64_t n) {
-        o = o_;
-        d = d_;
-        inv = safe_inv(d_);
-        tmin = tmin_;
-        self = self_;
-        self_leaf = self_leaf_;
-        T = 1.0f;
-        st.reset();
-        node = n > 1 ? 0 : -1;   // a single Gaussian is the source itself
-        budget = n;
-    }
-
-    // A malformed tree (never produced by the builder) ends the ray with NaN
-    // instead of looping or overflowing the stack.
-    __device__ __forceinline__ bool fail() {
-        node = -1;
-        T = __int_as_float(0x7fc00000);
-        return true;
-    }
-
-    // Visit four-wide node `node`: test its hit leaves in slot order (the exit
-    // checked after each), then continue with the first hit internal child,
-    // stacking the others so that they come off in slot order. Returns true
-    // when the ray is finished.
-    template <class OnHit, bool kCount = false>
-    __device__ __forceinline__ bool step(const float4 *__restrict__ nodes4, const float4 *__restrict__ rec,
-                                         const Cuts &c, OnHit &on_hit, int64_t *n_nodes = nullptr,
-                                         int64_t *n_leaves = nullptr, int64_t *n_hits = nullptr) {
-        if (--budget < 0) return fail();
-        int32_t id[4];
-        visit4(nodes4, node, o, inv, tmin, id);
-        if (kCount) ++*n_nodes;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (is_leaf(id[s])) {
-                const float f = leaf_factor(rec, ~id[s], o, d, tmin, self, self_leaf, c, on_hit, T);
-                if (kCount) { ++*n_leaves; *n_hits += (f != 1.0f); }
-                T *= f;
-                if (T < c.T_stop) {
-                    node = -1;
-                    return true;
-                }
-            }
-        }
-        int32_t nxt = -1;
-#pragma unroll
-        for (int s = 3; s >= 0; --s) {
-            if (id[s] >= 0) {
-                if (nxt >= 0) {
-                    if (st.full()) return fail();
-                    st.push(nxt);
-                }
-                nxt = id[s];
-            }
-        }
-        if (nxt >= 0) {
-            node = nxt;
-        } else if (!st.empty()) {
-            node = st.pop();
-        } else {
-            node = -1;
-            return true;
-        }
-        return false;
-    }
-};
-
 // Enqueue the pooled traversal of listed rays on `stream` (defined with the
 // traversal kernels): ray j is ids[j] + id_offset = i * K + k; its T goes to
 // out[ids[j]] (out_by_value) or out[j]. With count non-null, only the first
