@@ -60,6 +60,7 @@ def parse():
                     help="only run the streaming-copy probe (known-size reference for counters)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-shade", action="store_true", help="skip the PBR shading leg")
     ap.add_argument("--sur-train-samples", type=int, default=8_000_000)
     ap.add_argument("--sur-steps", type=int, default=2000)
     ap.add_argument("--sur-batch", type=int, default=16384)
@@ -140,6 +141,45 @@ def surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, plain_rays_per_s):
                           mfma_frac=MLP_FLOPS_PER_QUERY * R / mlp_s / 1e12 / BF16_PEAK_TFLOPS),
         ms=fb_s * 1000.0,
     )
+
+
+# FP32 operations per (Gaussian, direction) of the shading sum, counted from
+# the formulas: direction in the normal frame and its normalisation 15, the
+# two angles and the bilinear map lookup 30, the SH basis and its three dot
+# products 39, the microfacet specular 45, the accumulation 9
+SHADE_FLOPS = 138
+FP32_PEAK_TFLOPS = 157.3
+
+
+def shade_leg(torch, g, dirs, prm, vis_ray):
+    """Per-Gaussian PBR colour (Eq. (10)) from the traced visibility, with
+    seeded materials, environment map and camera."""
+    from paper_2311_16043_amd import shade_pbr
+    from workloads import materials
+    n, K = vis_ray.shape
+    m = materials.make_materials(n, 0)
+    dev = vis_ray.device
+    alb, rough, sh = (torch.from_numpy(m[k]).to(dev) for k in ("albedo", "roughness", "sh"))
+    env = torch.from_numpy(materials.make_env(0)).to(dev)
+    out = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    shade_pbr(g, dirs, vis_ray, alb, rough, sh, env, materials.CAMERA, params=prm, out=out)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        shade_pbr(g, dirs, vis_ray, alb, rough, sh, env, materials.CAMERA, params=prm, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    pairs = n * K
+    tflops = SHADE_FLOPS * pairs / (ms / 1000.0) / 1e12
+    hbm = (4 * pairs + n * 4 * (3 + 3 + 3 + 1 + 27 + 3)) / (ms / 1000.0) / 1e9
+    return dict(pairs=pairs, ms=ms, pairs_per_s=pairs / (ms / 1000.0), mean_color=float(out.mean()),
+                roofline={"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": tflops / FP32_PEAK_TFLOPS, "flops_per_pair": SHADE_FLOPS},
+                hbm_gbs=hbm)
 
 
 def adjoint_leg(torch, dev):
@@ -335,6 +375,9 @@ def main():
     if not args.no_surrogate and name != "tiny":
         out["surrogate"] = surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, rays / trace_s)
         print(f"[bench] surrogate: {json.dumps(out['surrogate'])}", file=sys.stderr, flush=True)
+    if not args.no_shade:
+        out["pbr"] = shade_leg(torch, g, dirs, prm, vis_ray)
+        print(f"[bench] pbr: {json.dumps(out['pbr'])}", file=sys.stderr, flush=True)
     if not args.no_adjoint and name == "object":
         out["adjoint"] = adjoint_leg(torch, dev)
         print(f"[bench] adjoint: {json.dumps(out['adjoint'])}", file=sys.stderr, flush=True)

@@ -335,6 +335,48 @@ rv_status rv_surrogate_infer(const void *params, const void *bvh, const rv_gauss
 rv_status rv_ray_setup(const rv_gaussians *g, const float *dirs, int32_t K, const rv_trace_params *p,
                        const int64_t *ray_ids, int64_t n, float *out_o, float *out_d, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Shading with pre-computed visibility (Sec. 3.3, Eq. (7)-(10))            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Material and light of rv_shade_pbr (device arrays, FP32, contiguous).
+ * albedo [n][3] in [0, 1]; roughness [n] in (0, 1] (GGX alpha = r^2);
+ * sh [n][9][3]: indirect light as real spherical harmonics of degree <= 2 per
+ * colour channel, basis order (0,0), (1,-1), (1,0), (1,1), (2,-2), (2,-1),
+ * (2,0), (2,1), (2,2) with the usual orthonormal constants (Y_00 = 1/(2
+ * sqrt(pi)), Y_1m = sqrt(3/(4 pi)) (y, z, x), ...); env [16][32][3]: direct
+ * light, equirectangular in the world frame with +z up, row 0 at the +z pole,
+ * column 0 at azimuth -pi, texel centres at half-integer coordinates,
+ * sampled bilinearly (wrapping in azimuth, clamped at the poles); camera:
+ * view position, w_o = normalize(camera - mu_i); f0: Fresnel reflectance at
+ * normal incidence (0.04 for a dielectric).
+ */
+typedef struct rv_pbr_material {
+    const float *albedo;
+    const float *roughness;
+    const float *sh;
+    const float *env;
+    float camera[3];
+    float f0;
+} rv_pbr_material;
+
+/*
+ * PBR colour of every Gaussian from its pre-computed visibility (Eq. (10)
+ * with the light of Eq. (9)): color[i] = sum_k (albedo_i / pi + f_s(w_o, w_k))
+ * (vis_ray[i][k] L_env(w_k) + L_sh_i(w_k)) max(n_i . w_k, 0) dw, where w_k are
+ * the visibility rays' directions (dirs, K, p->dir_mode as for
+ * rv_trace_visibility), dw = 2 pi / K (hemisphere) or 4 pi / K (sphere), and
+ * f_s = D F G / (4 (n . w_k)(n . w_o)) with GGX D (alpha = roughness^2),
+ * Schlick F (f0) and separable Smith G (0 when n . w_o <= 0).
+ * vis_ray: [n][K] FP32 (device), as written by rv_trace_visibility.
+ * color: [n][3] FP32 (device), overwritten. Normals are required.
+ * Errors: RV_ERR_INVALID_ARG (null pointers, n or K out of range, bad
+ * dir_mode), RV_ERR_HIP.
+ */
+rv_status rv_shade_pbr(const rv_gaussians *g, const float *dirs, int32_t K, const rv_trace_params *p,
+                       const float *vis_ray, const rv_pbr_material *m, float *color, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

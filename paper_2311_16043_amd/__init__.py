@@ -10,3 +10,4 @@ from .tracer import (BVH, Gaussians, TraceParams, build_bvh, trace_rays, trace_s
                      trace_visibility, trace_visibility_backward, stream_copy)
 from .autograd import VisibilityFn, visibility  # noqa: F401
 from .surrogate import Surrogate, ray_setup  # noqa: F401
+from .shading import shade_pbr  # noqa: F401

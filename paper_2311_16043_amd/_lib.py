@@ -47,6 +47,11 @@ class RvSurrogateArrays(C.Structure):
                 ("packed", C.c_void_p)]
 
 
+class RvPbrMaterial(C.Structure):
+    _fields_ = [("albedo", C.c_void_p), ("roughness", C.c_void_p), ("sh", C.c_void_p), ("env", C.c_void_p),
+                ("camera", C.c_float * 3), ("f0", C.c_float)]
+
+
 class RvError(RuntimeError):
     def __init__(self, fn: str, code: int, msg: str):
         super().__init__(f"{fn} failed with status {code}: {msg}")
@@ -83,6 +88,7 @@ SIGNATURES = {
     "rv_surrogate_infer": (_i32, [_vp, _vp, _PG, _vp, _i32, _PP, _i64, _i64, _f, _vp, _vp, _vp, _vp, _sz,
                                   _vp]),
     "rv_ray_setup": (_i32, [_PG, _vp, _i32, _PP, _vp, _i64, _vp, _vp, _vp]),
+    "rv_shade_pbr": (_i32, [_PG, _vp, _i32, _PP, _vp, C.POINTER(RvPbrMaterial), _vp, _vp]),
 }
 
 _lib = None
