@@ -55,6 +55,8 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(const float *__restrict__
     const float r = roughness[i];
     const float a2 = (r * r) * (r * r);
     const float g1o = no > 0.0f ? 2.0f * no / (no + sqrtf(a2 + (1.0f - a2) * no * no)) : 0.0f;
+    // per-Gaussian factor of the specular term: G1(w_o) / (4 pi (n . w_o)) times alpha^2
+    const float spec_k = no > 0.0f ? g1o * a2 / (4.0f * kPi * no) : 0.0f;
     const float kd0 = albedo[3 * i] * (1.0f / kPi), kd1 = albedo[3 * i + 1] * (1.0f / kPi),
                 kd2 = albedo[3 * i + 2] * (1.0f / kPi);
     float l[9][3];
@@ -76,8 +78,8 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(const float *__restrict__
         const float v = theta * ((float)kEnvRows / kPi) - 0.5f;
         const float uf = floorf(u), vf = floorf(v);
         const float fu = u - uf, fv = v - vf;
-        int c0 = (int)uf % kEnvCols;
-        if (c0 < 0) c0 += kEnvCols;
+        // u lies in [-0.5, 31.5): the left texel column is -1 (wraps to 31) .. 31
+        const int c0 = uf < 0.0f ? kEnvCols - 1 : (int)uf;
         const int c1 = c0 + 1 == kEnvCols ? 0 : c0 + 1;
         const int ra = min(max((int)vf, 0), kEnvRows - 1), rb = min(max((int)vf + 1, 0), kEnvRows - 1);
         float Le[3];
@@ -102,19 +104,20 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(const float *__restrict__
             Li[ch] = V * Le[ch] + s;
         }
         // specular times the cosine: D F G / (4 (n . w_o)); the GGX denominator
-        // uses 1 - (n.h)^2 = |n x h|^2 to stay accurate for smooth surfaces
+        // uses 1 - (n.h)^2 = |n x h|^2 to stay accurate for smooth surfaces.
+        // Hardware reciprocals (about 1 ulp) for the BRDF's quotients.
         float spec = 0.0f;
         if (no > 0.0f) {
             f3 h = w + wo;
-            h = (1.0f / sqrtf(dot(h, h))) * h;
+            h = __builtin_amdgcn_rsqf(dot(h, h)) * h;
             const float nh = fmaxf(dot(nrm, h), 0.0f), vh = fmaxf(dot(wo, h), 0.0f);
             const f3 nxh = cross(nrm, h);
             const float t = dot(nxh, nxh) + nh * nh * a2;
-            const float D = a2 / (kPi * t * t);
             const float m = 1.0f - vh, m2 = m * m;
             const float F = f0 + (1.0f - f0) * (m2 * m2 * m);
-            const float g1i = 2.0f * ci / (ci + sqrtf(a2 + (1.0f - a2) * ci * ci));
-            spec = D * F * g1i * g1o / (4.0f * no);
+            const float g1i_over_2ci = __builtin_amdgcn_rcpf(ci + sqrtf(a2 + (1.0f - a2) * ci * ci));
+            // D F G1(w_i) G1(w_o) / (4 n.w_o) with D = alpha^2 / (pi t^2)
+            spec = spec_k * F * (2.0f * ci * g1i_over_2ci) * __builtin_amdgcn_rcpf(t * t);
         }
         acc0 = fmaf((kd0 * ci + spec) * Li[0], dw, acc0);
         acc1 = fmaf((kd1 * ci + spec) * Li[1], dw, acc1);
