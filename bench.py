@@ -182,6 +182,64 @@ def shade_leg(torch, g, dirs, prm, vis_ray):
                 hbm_gbs=hbm)
 
 
+def retrace_leg(torch, g, prm, bvh, iters=20):
+    """Training-time tracing (Sec. 3.3 and 5.1): every iteration draws a new
+    turn of the 64 Fibonacci directions about each normal and re-traces all
+    Gaussians (vis_ray and vis_mean), table upload included."""
+    from paper_2311_16043_amd import trace_visibility
+    from workloads import scenes
+    rng = np.random.Generator(np.random.PCG64(16043 + 7))
+    dev = g.mean.device
+    K = 64
+    vr = torch.empty((g.n, K), dtype=torch.float32, device=dev)
+    vm = torch.empty((g.n,), dtype=torch.float32, device=dev)
+    tables = [scenes.rotated_dirs(K, float(a)) for a in rng.uniform(0, 2 * np.pi, iters + 2)]
+    trace_visibility(bvh, g, torch.from_numpy(tables[0]).to(dev), prm, out_ray=vr, out_mean=vm)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for it in range(iters):
+        trace_visibility(bvh, g, torch.from_numpy(tables[it + 1]).to(dev), prm, out_ray=vr, out_mean=vm)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / iters
+    return dict(directions=K, iterations=iters, ms_per_iteration=dt * 1000.0, rays_per_s=g.n * K / dt)
+
+
+def edit_leg(torch, sc, g, dirs, prm):
+    """Scene edit (Sec. 4.3): turn the sphere of the object scene by 0.5 rad
+    about the vertical and shift it by (0.8, 0.3, 0); update the tree by refit
+    (order and topology kept) or by a full rebuild, and trace both."""
+    from paper_2311_16043_amd import Gaussians, build_bvh, refit_bvh, trace_visibility
+    from workloads import scenes
+    dev = g.mean.device
+    sel = np.nonzero(sc["mean"][:, 2] > 0.05)[0]
+    g2 = Gaussians.from_scene(scenes.rigid_move(sc, sel, 0.5, [0.8, 0.3, 0.0]), device=dev)
+    bvh_r = build_bvh(g)
+    L = __import__("paper_2311_16043_amd")._lib.load()
+    ws = torch.empty(int(L.rv_build_workspace_bytes(g.n)), dtype=torch.uint8, device=dev)
+    vr = torch.empty((g.n, int(dirs.shape[0])), dtype=torch.float32, device=dev)
+    vm = torch.empty((g.n,), dtype=torch.float32, device=dev)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), r
+
+    refit_ms, _ = timed(lambda: refit_bvh(bvh_r, g2, workspace=ws))
+    build_ms, bvh_b = timed(lambda: build_bvh(g2, workspace=ws))
+    trace_refit_ms, _ = timed(lambda: trace_visibility(bvh_r, g2, dirs, prm, out_ray=vr, out_mean=vm))
+    trace_build_ms, _ = timed(lambda: trace_visibility(bvh_b, g2, dirs, prm, out_ray=vr, out_mean=vm))
+    return dict(moved=int(sel.size), refit_ms=refit_ms, rebuild_ms=build_ms, trace_after_refit_ms=trace_refit_ms,
+                trace_after_rebuild_ms=trace_build_ms)
+
+
 def adjoint_leg(torch, dev):
     """Forward and adjoint on the differentiation workload (200,000 Gaussians x
     128 hemisphere directions) with the loss L = mean_i (Vbar_i - y_i)^2: the
@@ -375,6 +433,11 @@ def main():
     if not args.no_surrogate and name != "tiny":
         out["surrogate"] = surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, rays / trace_s)
         print(f"[bench] surrogate: {json.dumps(out['surrogate'])}", file=sys.stderr, flush=True)
+    if name == "object":
+        out["edit"] = edit_leg(torch, sc, g, dirs, prm)
+        print(f"[bench] edit: {json.dumps(out['edit'])}", file=sys.stderr, flush=True)
+        out["retrace"] = retrace_leg(torch, g, prm, bvh)
+        print(f"[bench] retrace: {json.dumps(out['retrace'])}", file=sys.stderr, flush=True)
     if not args.no_shade:
         out["pbr"] = shade_leg(torch, g, dirs, prm, vis_ray)
         print(f"[bench] pbr: {json.dumps(out['pbr'])}", file=sys.stderr, flush=True)

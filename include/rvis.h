@@ -149,6 +149,21 @@ size_t rv_build_workspace_bytes(int64_t n);
 rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_bytes, void *ws, size_t ws_bytes,
                        void *stream);
 
+/*
+ * Refit a built BVH to moved Gaussians (scene edits and compositions,
+ * Sec. 4.3): g must be the set the blob was built from (same n, same
+ * indices), with any means, rotations, scales, opacities and normals. The
+ * build's sorted order, Morton keys and topology are kept; the means' box,
+ * leaf records, 3-sigma boxes, origin data, internal boxes and four-wide
+ * records are recomputed exactly as rv_build_bvh computes them. Traversal
+ * stays exact (boxes are recomputed, so they stay conservative); its cost
+ * grows as moved Gaussians drift from their neighbours in the old order, and
+ * a rebuild restores it. Same workspace as rv_build_bvh. With unchanged
+ * inputs the blob is reproduced bit for bit.
+ * Errors: as rv_build_bvh.
+ */
+rv_status rv_refit_bvh(const rv_gaussians *g, void *bvh, size_t bvh_bytes, void *ws, size_t ws_bytes, void *stream);
+
 /* Host-side decoding of a BVH blob into device pointers (no device access). */
 rv_status rv_bvh_view(const void *bvh, int64_t n, rv_bvh_arrays *out);
 

@@ -69,6 +69,7 @@ SIGNATURES = {
     "rv_bvh_bytes": (_sz, [_i64]),
     "rv_build_workspace_bytes": (_sz, [_i64]),
     "rv_build_bvh": (_i32, [_PG, _vp, _sz, _vp, _sz, _vp]),
+    "rv_refit_bvh": (_i32, [_PG, _vp, _sz, _vp, _sz, _vp]),
     "rv_bvh_view": (_i32, [_vp, _i64, C.POINTER(RvBvhArrays)]),
     "rv_trace_workspace_bytes": (_sz, [_i64, _i32]),
     "rv_trace_visibility": (_i32, [_vp, _PG, _vp, _i32, _PP, _vp, _vp, _vp, _sz, _vp]),

@@ -571,3 +571,46 @@ extern "C" rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
     }
     return check_launch("leaf records / karras / refit");
 }
+
+extern "C" rv_status rv_refit_bvh(const rv_gaussians *g, void *bvh, size_t bvh_bytes, void *ws, size_t ws_bytes,
+                                  void *stream) {
+    clear_error();
+    RV_REQUIRE(g && bvh && ws, RV_ERR_INVALID_ARG, "rv_refit_bvh: null argument (g, bvh or ws)");
+    RV_REQUIRE(g->mean && g->quat && g->log_scale && g->opacity, RV_ERR_INVALID_ARG,
+               "rv_refit_bvh: null Gaussian array");
+    const int64_t n = g->n;
+    RV_REQUIRE(n >= 1 && n <= RV_MAX_GAUSSIANS, RV_ERR_INVALID_ARG, "rv_refit_bvh: n=%lld out of range",
+               (long long)n);
+    RV_REQUIRE(((uintptr_t)bvh % kAlign) == 0 && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG,
+               "rv_refit_bvh: bvh and ws must be 256-byte aligned");
+    const BvhLayout L = bvh_layout(n);
+    const BuildWsLayout W = build_ws_layout(n);
+    RV_REQUIRE(bvh_bytes >= L.total, RV_ERR_WORKSPACE, "rv_refit_bvh: bvh_bytes %zu < %zu", bvh_bytes, L.total);
+    RV_REQUIRE(ws_bytes >= W.total, RV_ERR_WORKSPACE, "rv_refit_bvh: ws_bytes %zu < %zu", ws_bytes, W.total);
+    hipStream_t s = (hipStream_t)stream;
+    float *header = at<float>(bvh, L.header);
+    const uint32_t *perm = at<uint32_t>(bvh, L.perm);
+    float *nodes = at<float>(bvh, L.nodes);
+    const int32_t *parent = at<int32_t>(bvh, L.parent);
+    float4 *rec = at<float4>(bvh, L.leaf_rec);
+    float *box = at<float>(bvh, L.leaf_box);
+    float4 *orig = at<float4>(bvh, L.origins);
+    float *bpart = at<float>(ws, W.bounds);
+    uint32_t *flags = at<uint32_t>(ws, W.flags);
+    // the scene scale of the leaf widening follows the moved means; the sorted
+    // order, keys and topology stay as built
+    const int nb = (int)std::min<int64_t>(kBoundsBlocks, (n + 255) / 256);
+    hipLaunchKernelGGL(k_bounds_partial, dim3(nb), dim3(256), 0, s, g->mean, n, bpart);
+    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, bpart, nb, header, n);
+    hipLaunchKernelGGL(k_leaf_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, g->mean, g->quat, g->log_scale,
+                       g->opacity, g->normal, n, perm, header, rec, box, orig);
+    if (n > 1) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, flags, n - 1, 0u);
+        hipLaunchKernelGGL(k_refit, dim3(grid_for(n, 256)), dim3(256), 0, s, n, box, parent, nodes, flags, header);
+        hipLaunchKernelGGL(k_collapse4, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, n, nodes, header,
+                           at<float>(bvh, L.nodes4));
+    } else {
+        hipLaunchKernelGGL(k_refit, dim3(1), dim3(64), 0, s, n, box, parent, nodes, flags, header);
+    }
+    return check_launch("rv_refit_bvh");
+}

@@ -144,6 +144,22 @@ def _dirs(dirs, device) -> torch.Tensor:
                 (3,), "dirs", device)
 
 
+def refit_bvh(bvh: BVH, g: Gaussians, workspace: torch.Tensor | None = None) -> BVH:
+    """Refit `bvh` in place to the (moved) Gaussians it was built from: same
+    topology and order, boxes and records recomputed."""
+    L = _lib.load()
+    if g.n != bvh.n:
+        raise ValueError(f"refit_bvh: the BVH holds {bvh.n} Gaussians, g has {g.n}")
+    dev = g.mean.device
+    ws_bytes = L.rv_build_workspace_bytes(g.n)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc_bytes(ws_bytes, dev)
+    gc = g.c()
+    _lib.call("rv_refit_bvh", C.byref(gc), bvh.ptr, bvh.blob.numel(), workspace.data_ptr(), workspace.numel(),
+              _stream_ptr(dev))
+    return bvh
+
+
 def trace_visibility(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = None,
                      want_ray: bool = True, want_mean: bool = True, out_ray: torch.Tensor | None = None,
                      out_mean: torch.Tensor | None = None, workspace: torch.Tensor | None = None):

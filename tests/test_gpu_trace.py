@@ -63,6 +63,22 @@ def test_small_scenes_sampled(label, maker, K, count):
     check_vis(vr.reshape(-1)[ids], orc, label=label)
 
 
+def test_training_time_rotated_directions():
+    """Training re-traces each iteration with the 64 directions turned about
+    the normal by a fresh angle: three turns on one BVH, each against the
+    oracle with the same table."""
+    sc = scenes.make_object_scene(20_000, 1)
+    prm = TraceParams()
+    g = Gaussians.from_scene(sc)
+    bvh = build_bvh(g)
+    for it, angle in enumerate((0.3, 2.1, 5.0)):
+        dirs = scenes.rotated_dirs(64, angle)
+        vr, _ = trace_visibility(bvh, g, dirs, prm)
+        ids = scenes.sample_ray_ids(20_000, 64, 1024, seed=20 + it)
+        orc = oracle.trace_rays(sc, dirs, 1, ids, _oprm(prm))
+        check_vis(vr.cpu().numpy().reshape(-1)[ids], orc, label=f"rotated {angle}")
+
+
 def test_object_scale_full_size_sampled():
     """300,000 Gaussians x 256 hemisphere directions, traced in full in the
     benchmark's launch configuration; 4,096 seeded rays checked."""

@@ -297,6 +297,36 @@ def preset_dirs(name: str, K: int | None = None) -> np.ndarray:
     return fibonacci_dirs(K or cfg["K"], hemisphere=cfg["dir_mode"] == 1)
 
 
+def rotated_dirs(K: int, angle: float, hemisphere: bool = True) -> np.ndarray:
+    """Fibonacci directions turned by `angle` about the local z axis (the
+    normal in hemisphere mode), float32: the per-iteration resampling of the
+    incident directions during training."""
+    d = fibonacci_dirs(K, hemisphere).astype(np.float64)
+    c, s = math.cos(angle), math.sin(angle)
+    out = np.stack([c * d[:, 0] - s * d[:, 1], s * d[:, 0] + c * d[:, 1], d[:, 2]], 1)
+    return out.astype(np.float32)
+
+
+def rigid_move(scene: dict, sel, angle_z: float, shift) -> dict:
+    """Copy of the scene with Gaussians `sel` (index array or slice) turned by
+    angle_z about the vertical axis through their centroid and shifted: the
+    edit of an object in a composition (means, rotations and normals move
+    together; scales and opacities stay). float32 like the generators."""
+    out = {k: v.copy() for k, v in scene.items()}
+    mu = scene["mean"][sel].astype(np.float64)
+    c = mu.mean(0)
+    ca, sa = math.cos(angle_z), math.sin(angle_z)
+    R = np.array([[ca, -sa, 0.0], [sa, ca, 0.0], [0.0, 0.0, 1.0]])
+    out["mean"][sel] = ((mu - c) @ R.T + c + np.asarray(shift, np.float64)).astype(np.float32)
+    out["normal"][sel] = (scene["normal"][sel].astype(np.float64) @ R.T).astype(np.float32)
+    # quaternion of the turn, w-first, composed on the left: q' = r q
+    rw, rz = math.cos(angle_z / 2), math.sin(angle_z / 2)
+    q = scene["quat"][sel].astype(np.float64)
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    out["quat"][sel] = np.stack([rw * w - rz * z, rw * x - rz * y, rw * y + rz * x, rw * z + rz * w], 1).astype(np.float32)
+    return out
+
+
 def sample_ray_ids(n: int, K: int, count: int, seed: int) -> np.ndarray:
     """Seeded uniform sample of distinct ray ids r = i*K + k (int64, sorted)."""
     total = n * K
