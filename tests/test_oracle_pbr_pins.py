@@ -179,3 +179,43 @@ def test_sum_is_linear_in_visibility_and_brute_force_on_a_tiny_case():
                              pbr.smith_G1(wo @ n, a) / (4.0 * ci * (wo @ n)))
             acc += (m64["albedo"][i] / math.pi + spec) * light * max(ci, 0.0) * 2 * math.pi / 5
         assert np.allclose(c[i], acc, rtol=1e-12, atol=1e-14)
+
+
+# ---- visibility compressed to SH (oracle/vis_sh.py) ----
+
+from oracle import vis_sh  # noqa: E402
+
+
+def test_sh_projection_of_constant_and_of_a_cap():
+    K = 256
+    dirs = scenes.fibonacci_dirs(K, True)
+    # constant visibility c: v_00 = c Y_00 2 pi = c sqrt(pi) (the weights sum to 2 pi exactly)
+    v = vis_sh.project(np.full((1, K), 0.7), dirs, 1)
+    assert v[0, 0] == pytest.approx(0.7 * math.sqrt(math.pi), rel=1e-12)
+    # visibility 1 on the cap z > 1/2 (exactly the first K/2 Fibonacci samples):
+    # v_00 = Y_00 pi and v_10 = sqrt(3/(4 pi)) sum z dw = sqrt(3/(4 pi)) 3 pi / 4
+    # (the equal-area z spacing integrates z exactly)
+    cap = (dirs[:, 2].astype(np.float64) > 0.5).astype(np.float64)[None]
+    assert cap.sum() == K // 2
+    v = vis_sh.project(cap, dirs, 1)
+    assert v[0, 0] == pytest.approx(0.5 / math.sqrt(math.pi) * math.pi, rel=1e-6)
+    assert v[0, 2] == pytest.approx(math.sqrt(3 / (4 * math.pi)) * 0.75 * math.pi, rel=1e-6)
+
+
+def test_sh_projection_recovers_each_basis_function():
+    # sphere mode with many directions: projecting Y_j returns the unit vector e_j
+    dirs = scenes.fibonacci_dirs(40_000, False)
+    Y = pbr.sh_basis(dirs.astype(np.float64) / np.linalg.norm(dirs.astype(np.float64), axis=1, keepdims=True))
+    v = vis_sh.project(Y.T, dirs, 0)
+    assert np.allclose(v, np.eye(9), atol=2e-4)
+
+
+def test_sh_projection_bounds_bracket_every_visibility_in_between():
+    rng = np.random.default_rng(3)
+    dirs = scenes.fibonacci_dirs(64, True)
+    lo = rng.uniform(0, 0.5, (20, 64))
+    hi = lo + rng.uniform(0, 0.3, (20, 64))
+    blo, bhi = vis_sh.project_bounds(lo, hi, dirs, 1)
+    for _ in range(20):
+        v = vis_sh.project(lo + rng.uniform(0, 1, lo.shape) * (hi - lo), dirs, 1)
+        assert np.all(v >= blo - 1e-12) and np.all(v <= bhi + 1e-12)
