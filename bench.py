@@ -240,6 +240,28 @@ def edit_leg(torch, sc, g, dirs, prm):
                 trace_after_rebuild_ms=trace_build_ms)
 
 
+def vis_sh_leg(torch, g, dirs, prm, bvh):
+    """Visibility compressed to 9 SH coefficients per Gaussian, traced with no
+    per-ray output (same rays as the step)."""
+    from paper_2311_16043_amd import trace_visibility_sh
+    n, K = g.n, int(dirs.shape[0])
+    L = __import__("paper_2311_16043_amd")._lib.load()
+    ws = torch.empty(int(L.rv_trace_sh_workspace_bytes(n, K)), dtype=torch.uint8, device=g.mean.device)
+    trace_visibility_sh(bvh, g, dirs, prm, workspace=ws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        trace_visibility_sh(bvh, g, dirs, prm, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    return dict(ms=ms, rays_per_s=n * K / (ms / 1000.0), output_bytes=n * 9 * 4, per_ray_output_bytes=n * K * 4,
+                workspace_bytes=int(ws.numel()))
+
+
 def adjoint_leg(torch, dev):
     """Forward and adjoint on the differentiation workload (200,000 Gaussians x
     128 hemisphere directions) with the loss L = mean_i (Vbar_i - y_i)^2: the
@@ -438,6 +460,8 @@ def main():
         print(f"[bench] edit: {json.dumps(out['edit'])}", file=sys.stderr, flush=True)
         out["retrace"] = retrace_leg(torch, g, prm, bvh)
         print(f"[bench] retrace: {json.dumps(out['retrace'])}", file=sys.stderr, flush=True)
+    out["vis_sh"] = vis_sh_leg(torch, g, dirs, prm, bvh)
+    print(f"[bench] vis_sh: {json.dumps(out['vis_sh'])}", file=sys.stderr, flush=True)
     if not args.no_shade:
         out["pbr"] = shade_leg(torch, g, dirs, prm, vis_ray)
         print(f"[bench] pbr: {json.dumps(out['pbr'])}", file=sys.stderr, flush=True)

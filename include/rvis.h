@@ -199,6 +199,26 @@ rv_status rv_trace_rays(const void *bvh, const rv_gaussians *g, const float *dir
                         const rv_trace_params *p, const int64_t *ray_ids, int64_t n_rays, float *out,
                         void *stream);
 
+/* Bytes of the workspace of rv_trace_visibility_sh. */
+size_t rv_trace_sh_workspace_bytes(int64_t n, int32_t K);
+
+/*
+ * Visibility compressed to spherical harmonics, without per-ray output: the
+ * same rays and transmittances as rv_trace_visibility (the same traversal, so
+ * the same T for every ray), each Gaussian's K values projected onto the real
+ * SH of degree <= 2 (the "3-level SH" of Sec. 3.3) by the quadrature of
+ * Eq. (10): vis_sh[i][j] = sum_k T_ik Y_j(d_k) dw, dw = 2 pi / K (hemisphere)
+ * or 4 pi / K (sphere), d_k the table's unit directions in the rays' frame
+ * (local about the normal in hemisphere mode), basis order (0,0), (1,-1),
+ * (1,0), (1,1), (2,-2), (2,-1), (2,0), (2,1), (2,2). vis_mean (optional) is
+ * the mean of T over the K directions. Deterministic (fixed summation order).
+ * vis_sh: [n][9] FP32 (device); ws: rv_trace_sh_workspace_bytes(n, K) bytes,
+ * 256-byte aligned. Errors: as rv_trace_visibility, RV_ERR_WORKSPACE.
+ */
+rv_status rv_trace_visibility_sh(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
+                                 const rv_trace_params *p, float *vis_sh, float *vis_mean, void *ws, size_t ws_bytes,
+                                 void *stream);
+
 /*
  * Traversal statistics of rv_trace_visibility's rays: writes (device)
  * totals[0] = four-wide node visits, totals[1] = leaf records tested,

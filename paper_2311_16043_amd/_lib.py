@@ -89,6 +89,8 @@ SIGNATURES = {
     "rv_surrogate_infer": (_i32, [_vp, _vp, _PG, _vp, _i32, _PP, _i64, _i64, _f, _vp, _vp, _vp, _vp, _sz,
                                   _vp]),
     "rv_ray_setup": (_i32, [_PG, _vp, _i32, _PP, _vp, _i64, _vp, _vp, _vp]),
+    "rv_trace_sh_workspace_bytes": (_sz, [_i64, _i32]),
+    "rv_trace_visibility_sh": (_i32, [_vp, _PG, _vp, _i32, _PP, _vp, _vp, _vp, _sz, _vp]),
     "rv_shade_pbr": (_i32, [_PG, _vp, _i32, _PP, _vp, C.POINTER(RvPbrMaterial), _vp, _vp]),
 }
 

@@ -372,6 +372,214 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool_list(
     }
 }
 
+// ---- visibility compressed to SH ----------------------------------------------
+//
+// Each Gaussian's visibility over its K directions projected onto the real
+// spherical harmonics of degree <= 2 (9 coefficients, the "3-level SH" of
+// Sec. 3.3) by the quadrature of Eq. (10): v_ij = sum_k V_ik Y_j(d_k) dw, with
+// d_k the table's unit directions in the rays' frame (local about the normal
+// in hemisphere mode). No per-ray output: a wave takes 64 adjacent Gaussians
+// through a run of direction chunks, draining each chunk's pool as the
+// all-ray kernel does, and each lane adds its Gaussian's rays in a fixed order.
+// A few runs per Gaussian group keep enough waves in flight; their FP64
+// partials are added in run order (deterministic).
+constexpr int kShCoef = 9;
+constexpr int kShSums = kShCoef + 1;   // the 9 projections and the plain sum of V
+constexpr int64_t kShTargetWaves = 65536;
+
+struct ShMap {
+    int64_t n;
+    int K, n_chunks, n_runs, chunks_per_run;
+    int64_t n_items;   // ceil(n / 64) * n_runs
+    int64_t w_off;
+};
+
+inline ShMap make_sh_map(int64_t n, int K) {
+    ShMap m;
+    m.n = n;
+    m.K = K;
+    m.n_chunks = (K + kPoolS - 1) / kPoolS;
+    const int64_t groups = (n + 63) / 64;
+    int64_t runs = (kShTargetWaves + groups - 1) / groups;
+    runs = std::max<int64_t>(1, std::min<int64_t>(runs, m.n_chunks));
+    m.chunks_per_run = (int)((m.n_chunks + runs - 1) / runs);
+    m.n_runs = (m.n_chunks + m.chunks_per_run - 1) / m.chunks_per_run;
+    m.n_items = groups * (int64_t)m.n_runs;
+    m.w_off = 0;
+    return m;
+}
+
+// Real SH of degree <= 2 at the unit direction of table entry k.
+__device__ __forceinline__ void sh_of_dir(const float *__restrict__ dirs, int k, float (&Y)[kShCoef]) {
+    float x = dirs[3 * k], y = dirs[3 * k + 1], z = dirs[3 * k + 2];
+    const float inv = 1.0f / sqrtf(x * x + y * y + z * z);
+    x *= inv; y *= inv; z *= inv;
+    Y[0] = 0.28209479177387814f;
+    Y[1] = 0.4886025119029199f * y;
+    Y[2] = 0.4886025119029199f * z;
+    Y[3] = 0.4886025119029199f * x;
+    Y[4] = 1.0925484305920792f * x * y;
+    Y[5] = 1.0925484305920792f * y * z;
+    Y[6] = 0.31539156525252005f * (3.0f * z * z - 1.0f);
+    Y[7] = 1.0925484305920792f * x * z;
+    Y[8] = 0.5462742152960396f * (x * x - y * y);
+}
+
+constexpr int kShRing = 8;   // direction rows held in the result ring
+
+__global__ __launch_bounds__(kTraceBlock) void k_trace_sh(const float4 *__restrict__ nodes4,
+                                                          const float4 *__restrict__ rec,
+                                                          const float4 *__restrict__ origins,
+                                                          const float *__restrict__ dirs, ShMap sm, Cuts c,
+                                                          double *__restrict__ partial) {
+    __shared__ int32_t stk[kPoolRing * kTraceBlock];
+    __shared__ int32_t fifo[kFifo * kTraceBlock];
+    __shared__ float ring[kWavesPerBlock][kShRing * 64];
+    __shared__ int32_t done_cnt[kWavesPerBlock][kShRing];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t w = sm.w_off + xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+    if (w >= sm.n_items) return;  // wave-uniform
+    const int64_t grp = w / sm.n_runs;
+    const int run = (int)(w - grp * sm.n_runs);
+    GridSource src;
+    src.rec = rec;
+    src.origins = origins;
+    src.dirs = dirs;
+    src.m0 = grp * 64;
+    src.nv = (int)min<int64_t>(64, sm.n - src.m0);
+    src.k0 = run * sm.chunks_per_run * kPoolS;
+    src.dir_mode = c.dir_mode;
+    src.tmin_scale = c.tmin_scale;
+    const int nv = src.nv;
+    // the run's directions k0 .. k0 + rows - 1, one row of nv rays each;
+    // pool index idx = row * nv + origin
+    const int rows = min(sm.chunks_per_run * kPoolS, sm.K - src.k0);
+    const int pool_n = rows * nv;
+    if (lane < kShRing) done_cnt[wv][lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+
+    float acc[kShSums];
+#pragma unroll
+    for (int q = 0; q < kShSums; ++q) acc[q] = 0.0f;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    RingStack<kPoolRing> st;
+    int32_t spill[RingStack<kPoolRing>::kSpill];
+    st.lds = stk + threadIdx.x;
+    st.spill = spill;
+    st.stride = kTraceBlock;
+    st.sp = 0;
+    int32_t *my_fifo = fifo + threadIdx.x;
+    int fhead = 0, fcount = 0;
+    bool has = false;
+    int row = 0, oi = 0;  // direction row and origin of the current ray
+    f3 o = mk(0.f, 0.f, 0.f), d = o, inv = o;
+    float tmin = 0.f, T = 1.f;
+    int32_t self = -1, self_leaf = -1, node = -1;
+    int64_t budget = 0, cn = 0;
+    NoHit none;
+    int next = 0;      // next pool index to hand out (wave-uniform)
+    int consumed = 0;  // rows already added to the sums (wave-uniform)
+
+    while (consumed < rows) {
+        // refill idle lanes, never more than kShRing rows ahead of the sums
+        const int avail = min(pool_n, (consumed + kShRing) * nv);
+        const uint64_t need = __ballot(!has);
+        if (need != 0 && next < avail) {
+            const int idx = next + __popcll(need & lt);
+            if (!has && idx < avail) {
+                const RaySetup r = src(idx);
+                o = r.o;
+                d = r.d;
+                inv = safe_inv(d);
+                tmin = r.tmin;
+                self = r.self;
+                self_leaf = r.self_leaf;
+                T = 1.0f;
+                st.sp = 0;
+                fhead = 0;
+                fcount = 0;
+                node = sm.n > 1 ? 0 : -1;
+                budget = sm.n;
+                row = idx / nv;
+                oi = idx - row * nv;
+                has = true;
+            }
+            next = min(avail, next + __popcll(need));
+        }
+
+        if (has && node >= 0 && fcount <= kFifo - 4)
+            pool_node_step<false>(nodes4, o, inv, tmin, node, budget, st, my_fifo, fhead, fcount, T, cn);
+
+        if (leaf_phase_now(has, node, fcount)) {
+            if (has && fcount > 0) {
+                const int32_t leaf = my_fifo[fhead * kTraceBlock];
+                fhead = (fhead + 1) & (kFifo - 1);
+                --fcount;
+                T *= leaf_factor(rec, leaf, o, d, tmin, self, self_leaf, c, none, T);
+                if (T < c.T_stop) {
+                    node = -1;
+                    fcount = 0;
+                }
+            }
+        }
+
+        // finished rays park T in their row's ring slot and count the row
+        const bool finished = has && node < 0 && fcount == 0;
+        if (finished) {
+            const int slot = row & (kShRing - 1);
+            ring[wv][slot * 64 + oi] = T;
+            atomicAdd(&done_cnt[wv][slot], 1);
+            has = false;
+        }
+        if (__ballot(finished) == 0) continue;  // no row can have completed
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        // add completed rows to the sums strictly in row order (deterministic);
+        // every lane reads the same counter, so the loop is wave-uniform
+        while (consumed < rows && done_cnt[wv][consumed & (kShRing - 1)] == nv) {
+            const int slot = consumed & (kShRing - 1);
+            if (lane < nv) {
+                const float t = ring[wv][slot * 64 + lane];
+                float Y[kShCoef];
+                sh_of_dir(dirs, src.k0 + consumed, Y);
+#pragma unroll
+                for (int q = 0; q < kShCoef; ++q) acc[q] = fmaf(t, Y[q], acc[q]);
+                acc[kShCoef] += t;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) done_cnt[wv][slot] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            ++consumed;
+        }
+    }
+    if (lane < nv) {
+        const int64_t me = __float_as_int(rec[kLeafF4 * (src.m0 + lane) + 2].w);
+#pragma unroll
+        for (int q = 0; q < kShSums; ++q) partial[((int64_t)run * kShSums + q) * sm.n + me] = (double)acc[q];
+    }
+}
+
+// vis_sh[i][j] = dw * (sum over runs, in run order, of the partials);
+// vis_mean[i] = (sum of V over runs) / K.
+__global__ __launch_bounds__(256) void k_sh_from_partials(const double *__restrict__ partial, int64_t n, int n_runs,
+                                                          int K, double dw, float *__restrict__ vis_sh,
+                                                          float *__restrict__ vis_mean) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s[kShSums];
+#pragma unroll
+    for (int q = 0; q < kShSums; ++q) s[q] = 0.0;
+    for (int r = 0; r < n_runs; ++r)
+#pragma unroll
+        for (int q = 0; q < kShSums; ++q) s[q] += partial[((int64_t)r * kShSums + q) * n + i];
+#pragma unroll
+    for (int q = 0; q < kShCoef; ++q) vis_sh[i * kShCoef + q] = (float)(s[q] * dw);
+    if (vis_mean) vis_mean[i] = (float)(s[kShCoef] / (double)K);
+}
+
 // vis_mean[i] = (sum over chunks, in chunk order, of the FP64 partials) / K.
 __global__ __launch_bounds__(256) void k_mean_from_partials(const double *__restrict__ partial, int64_t n,
                                                             int n_chunks, int K, float *__restrict__ vis_mean) {
@@ -751,4 +959,39 @@ extern "C" rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaus
                            part, c, grad_vis_ray, grad_vis_mean, vis_ray_fwd, grad_opacity, grad_mean, grad_log_scale);
     }
     return check_launch("rv_trace_visibility_backward");
+}
+
+extern "C" size_t rv_trace_sh_workspace_bytes(int64_t n, int32_t K) {
+    if (n < 1 || K < 1) return 0;
+    const ShMap sm = make_sh_map(n, K);
+    return align_up((size_t)sm.n_runs * kShSums * (size_t)n * sizeof(double));
+}
+
+extern "C" rv_status rv_trace_visibility_sh(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
+                                            const rv_trace_params *p, float *vis_sh, float *vis_mean, void *ws,
+                                            size_t ws_bytes, void *stream) {
+    clear_error();
+    rv_status st = validate_trace("rv_trace_visibility_sh", bvh, g, dirs, K, p);
+    if (st != RV_OK) return st;
+    RV_REQUIRE(vis_sh, RV_ERR_INVALID_ARG, "rv_trace_visibility_sh: null vis_sh");
+    const size_t need = rv_trace_sh_workspace_bytes(g->n, K);
+    RV_REQUIRE(ws && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG,
+               "rv_trace_visibility_sh: ws missing or unaligned");
+    RV_REQUIRE(ws_bytes >= need, RV_ERR_WORKSPACE, "rv_trace_visibility_sh: ws_bytes %zu < %zu", ws_bytes, need);
+    const ShMap sm = make_sh_map(g->n, K);
+    const BvhLayout L = bvh_layout(g->n);
+    const Cuts c = make_cuts(*p);
+    hipStream_t s = (hipStream_t)stream;
+    double *partial = static_cast<double *>(ws);
+    for (int64_t w0 = 0; w0 < sm.n_items; w0 += kLaunchWaves) {
+        ShMap part = sm;
+        part.w_off = w0;
+        const int64_t nb = (std::min(kLaunchWaves, sm.n_items - w0) + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL(k_trace_sh, dim3((unsigned)nb), dim3(kTraceBlock), 0, s, at<float4>(bvh, L.nodes4),
+                           at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, part, c, partial);
+    }
+    const double dw = (p->dir_mode ? 2.0 : 4.0) * 3.14159265358979323846 / (double)K;
+    hipLaunchKernelGGL(k_sh_from_partials, dim3(grid_for(g->n, 256)), dim3(256), 0, s, partial, g->n, sm.n_runs, K,
+                       dw, vis_sh, vis_mean);
+    return check_launch("rv_trace_visibility_sh");
 }

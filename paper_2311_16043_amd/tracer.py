@@ -180,6 +180,25 @@ def trace_visibility(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = 
     return vr, vm
 
 
+def trace_visibility_sh(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = None, want_mean: bool = True,
+                        workspace: torch.Tensor | None = None):
+    """(vis_sh [n, 9], vis_mean [n] or None): each Gaussian's visibility
+    projected onto the degree-2 real SH, with no per-ray output."""
+    params = params or TraceParams()
+    dev = g.mean.device
+    d = _dirs(dirs, dev)
+    K = int(d.shape[0])
+    sh = torch.empty((g.n, 9), dtype=_F32, device=dev)
+    vm = torch.empty((g.n,), dtype=_F32, device=dev) if want_mean else None
+    ws_bytes = _lib.load().rv_trace_sh_workspace_bytes(g.n, K)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc_bytes(ws_bytes, dev)
+    gc, pc = g.c(), params.c()
+    _lib.call("rv_trace_visibility_sh", bvh.ptr, C.byref(gc), d.data_ptr(), K, C.byref(pc), sh.data_ptr(),
+              None if vm is None else vm.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_ptr(dev))
+    return sh, vm
+
+
 def trace_rays(bvh: BVH, g: Gaussians, dirs, ray_ids, params: TraceParams | None = None) -> torch.Tensor:
     """T of each listed ray id r = i*K + k (same bits as trace_visibility)."""
     params = params or TraceParams()
