@@ -407,7 +407,8 @@ typedef struct rv_pbr_material {
  * vis_ray: [n][K] FP32 (device), as written by rv_trace_visibility.
  * color: [n][3] FP32 (device), overwritten. Normals are required.
  * Errors: RV_ERR_INVALID_ARG (null pointers, n or K out of range, bad
- * dir_mode), RV_ERR_HIP.
+ * dir_mode, f0 outside [0, 1], a camera coordinate that is not finite),
+ * RV_ERR_HIP.
  */
 rv_status rv_shade_pbr(const rv_gaussians *g, const float *dirs, int32_t K, const rv_trace_params *p,
                        const float *vis_ray, const rv_pbr_material *m, float *color, void *stream);

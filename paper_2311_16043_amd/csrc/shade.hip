@@ -12,6 +12,8 @@
 // Mapping: one wave per Gaussian, lanes striding over the directions; the
 // Gaussian's parameters are wave-uniform, the map sits in LDS, and the three
 // colour sums end with a wave reduction.
+#include <cmath>
+
 #include "trace_core.h"
 
 namespace rv {
@@ -148,6 +150,9 @@ extern "C" rv_status rv_shade_pbr(const rv_gaussians *g, const float *dirs, int3
                (long long)g->n);
     RV_REQUIRE(K >= 1, RV_ERR_INVALID_ARG, "rv_shade_pbr: K=%d must be >= 1", K);
     RV_REQUIRE(p->dir_mode == 0 || p->dir_mode == 1, RV_ERR_INVALID_ARG, "rv_shade_pbr: dir_mode must be 0 or 1");
+    RV_REQUIRE(m->f0 >= 0.0f && m->f0 <= 1.0f, RV_ERR_INVALID_ARG, "rv_shade_pbr: f0 must lie in [0, 1]");
+    RV_REQUIRE(std::isfinite(m->camera[0]) && std::isfinite(m->camera[1]) && std::isfinite(m->camera[2]),
+               RV_ERR_INVALID_ARG, "rv_shade_pbr: camera position is not finite");
     // one wave per Gaussian, at most 2^24 waves (2^30 work-items) per grid
     const int64_t waves_per_block = kShadeBlock / 64, per_launch = int64_t(1) << 24;
     for (int64_t i0 = 0; i0 < g->n; i0 += per_launch) {

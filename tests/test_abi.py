@@ -119,6 +119,87 @@ def test_trace_rejects_bad_arguments(lib):
     assert lib.rv_trace_stats(P, C.byref(g), P, 8, C.byref(p), None, None, 0, None) == _lib.RV_ERR_INVALID_ARG
 
 
+def test_refit_rejects_bad_arguments(lib):
+    P = 1 << 40
+    g = _g()
+    ok_bytes = lib.rv_bvh_bytes(10)
+    ws = lib.rv_build_workspace_bytes(10)
+    f = lib.rv_refit_bvh
+    assert f(None, P, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert f(C.byref(g), None, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert f(C.byref(g), P, ok_bytes, None, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert f(C.byref(_g(0)), P, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert f(C.byref(g), P + 8, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert f(C.byref(g), P, ok_bytes - 256, P, ws, None) == _lib.RV_ERR_WORKSPACE
+    assert f(C.byref(g), P, ok_bytes, P, ws - 256, None) == _lib.RV_ERR_WORKSPACE
+    bad = _g()
+    bad.opacity = None
+    assert f(C.byref(bad), P, ok_bytes, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+
+
+def test_sh_workspace_and_rejects_bad_arguments(lib):
+    assert lib.rv_trace_sh_workspace_bytes(0, 8) == 0
+    assert lib.rv_trace_sh_workspace_bytes(10, 0) == 0
+    prev = 0
+    for n, K in ((1, 1), (10, 8), (1000, 256), (300_000, 256)):
+        b = lib.rv_trace_sh_workspace_bytes(n, K)
+        # at least one run of 10 FP64 sums per Gaussian, 256-byte aligned
+        assert b % 256 == 0 and b >= n * 10 * 8 and b >= prev
+        prev = b
+    P = 1 << 40
+    g = _g()
+    p = _params()
+    ws = lib.rv_trace_sh_workspace_bytes(10, 8)
+    f = lib.rv_trace_visibility_sh
+    assert f(P, C.byref(g), P, 8, C.byref(p), None, None, P, ws, None) == _lib.RV_ERR_INVALID_ARG  # no vis_sh
+    assert f(P, C.byref(g), P, 0, C.byref(p), P, None, P, ws, None) == _lib.RV_ERR_INVALID_ARG  # K = 0
+    assert f(P, C.byref(g), P, 8, C.byref(p), P, None, None, ws, None) == _lib.RV_ERR_INVALID_ARG  # no ws
+    assert f(P, C.byref(g), P, 8, C.byref(p), P, None, P + 16, ws, None) == _lib.RV_ERR_INVALID_ARG  # unaligned
+    assert f(P, C.byref(g), P, 8, C.byref(p), P, None, P, ws - 256, None) == _lib.RV_ERR_WORKSPACE
+    bad = _params(dir_mode=3)
+    assert f(P, C.byref(g), P, 8, C.byref(bad), P, None, P, ws, None) == _lib.RV_ERR_INVALID_ARG
+
+
+def _material(**kw):
+    P = 1 << 40
+    m = _lib.RvPbrMaterial(P, P, P, P, (C.c_float * 3)(0.0, 0.0, 3.0), 0.04)
+    for k, v in kw.items():
+        if k == "camera":
+            m.camera = (C.c_float * 3)(*v)
+        else:
+            setattr(m, k, v)
+    return m
+
+
+@pytest.mark.parametrize("bad", [dict(albedo=None), dict(roughness=None), dict(sh=None), dict(env=None),
+                                 dict(f0=-0.1), dict(f0=1.5), dict(f0=float("nan")),
+                                 dict(camera=(0.0, float("inf"), 1.0)), dict(camera=(float("nan"), 0.0, 1.0))])
+def test_shade_rejects_bad_material(lib, bad):
+    P = 1 << 40
+    g = _g()
+    p = _params()
+    m = _material(**bad)
+    assert lib.rv_shade_pbr(C.byref(g), P, 8, C.byref(p), P, C.byref(m), P, None) == _lib.RV_ERR_INVALID_ARG
+    assert b"rv_shade_pbr" in lib.rv_last_error()
+
+
+def test_shade_rejects_bad_arguments(lib):
+    P = 1 << 40
+    g = _g()
+    p = _params()
+    m = _material()
+    f = lib.rv_shade_pbr
+    assert f(None, P, 8, C.byref(p), P, C.byref(m), P, None) == _lib.RV_ERR_INVALID_ARG
+    assert f(C.byref(g), P, 0, C.byref(p), P, C.byref(m), P, None) == _lib.RV_ERR_INVALID_ARG  # K = 0
+    assert f(C.byref(g), P, 8, C.byref(p), None, C.byref(m), P, None) == _lib.RV_ERR_INVALID_ARG  # no vis
+    assert f(C.byref(g), P, 8, C.byref(p), P, None, P, None) == _lib.RV_ERR_INVALID_ARG  # no material
+    assert f(C.byref(g), P, 8, C.byref(p), P, C.byref(m), None, None) == _lib.RV_ERR_INVALID_ARG  # no output
+    assert f(C.byref(_g(normal=False)), P, 8, C.byref(p), P, C.byref(m), P, None) == _lib.RV_ERR_INVALID_ARG
+    assert f(C.byref(_g(0)), P, 8, C.byref(p), P, C.byref(m), P, None) == _lib.RV_ERR_INVALID_ARG
+    bad = _params(dir_mode=2)
+    assert f(C.byref(g), P, 8, C.byref(bad), P, C.byref(m), P, None) == _lib.RV_ERR_INVALID_ARG
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
     monkeypatch.setattr(_lib, "_lib", None)
