@@ -72,8 +72,10 @@ inline PoolMap make_pool(int64_t n, int K) {
 
 // One node visit of a pooled ray: hit leaves are appended to the lane's FIFO
 // (slot order), the first hit internal child becomes the next node and the
-// others are stacked to come off in slot order. A malformed tree (visit
-// budget spent, stack full) ends the ray with NaN.
+// others are stacked to come off in slot order. The stack holds at most three
+// siblings per wide level above the node, so in a tree of the bounded depth a
+// visit starts with room for its three pushes; a malformed tree (visit budget
+// spent, less room than that) ends the ray with NaN.
 template <bool kCount>
 __device__ __forceinline__ void pool_node_step(const float4 *__restrict__ nodes4, f3 o, f3 inv, float tmin,
                                                int32_t &node, int64_t &budget, RingStack<kPoolRing> &st,
@@ -95,15 +97,14 @@ __device__ __forceinline__ void pool_node_step(const float4 *__restrict__ nodes4
         }
     }
     int32_t nxt = -1;
-    bool overflow = false;
+    const bool overflow = st.sp > kMaxStack - 3;
+    if (!overflow) {
 #pragma unroll
-    for (int s = 3; s >= 0; --s) {
-        if (id[s] >= 0) {
-            if (nxt >= 0) {
-                if (st.full()) overflow = true;
-                else st.push(nxt);
+        for (int s = 3; s >= 0; --s) {
+            if (id[s] >= 0) {
+                if (nxt >= 0) st.push(nxt);
+                nxt = id[s];
             }
-            nxt = id[s];
         }
     }
     if (overflow) {
@@ -234,8 +235,13 @@ struct GridSource {
     int64_t m0;
     int nv, k0, dir_mode;
     float tmin_scale;
+    float inv_nv;  // reciprocal of nv (within one ulp)
     __device__ __forceinline__ RaySetup operator()(int idx) const {
-        const int oi = idx % nv, j = idx / nv;
+        // idx / nv from the float quotient: (idx + 1/2) / nv lies at least
+        // 1/(2 nv) >= 1/128 from an integer, far beyond its rounding error
+        // (idx < 2^9: below 2^9 2^-22)
+        const int j = (int)(((float)idx + 0.5f) * inv_nv);
+        const int oi = idx - j * nv;
         const int64_t m = m0 + oi;
         const float4 r0 = rec[kLeafF4 * m];
         const float4 og = origins[m];
@@ -263,12 +269,24 @@ struct ListSource {
     float tmin_scale;
     const int64_t *ids;
     int64_t id_offset, base;
+    double inv_k;  // 1 / K
     __device__ __forceinline__ RaySetup operator()(int idx) const {
         RaySetup r;
         const int64_t rid = ids[base + idx] + id_offset;
         r.valid = rid >= 0 && rid < n * (int64_t)K;
-        const int64_t i = r.valid ? rid / K : 0;
-        const int k = (int)(rid - i * K);
+        // rid / K from the FP64 quotient (off by at most one for rid < 2^52,
+        // where rid converts exactly), corrected so that 0 <= k < K; integer
+        // division beyond
+        int64_t i = !r.valid ? 0 : rid < (int64_t(1) << 52) ? (int64_t)((double)rid * inv_k) : rid / K;
+        int64_t k64 = r.valid ? rid - i * K : 0;
+        if (k64 < 0) {
+            --i;
+            k64 += K;
+        } else if (k64 >= K) {
+            ++i;
+            k64 -= K;
+        }
+        const int k = (int)k64;
         float nx = 0.f, ny = 0.f, nz = 1.f;
         if (normal) {
             nx = normal[3 * i]; ny = normal[3 * i + 1]; nz = normal[3 * i + 2];
@@ -309,6 +327,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
     src.dirs = dirs;
     src.m0 = grp * 64;
     src.nv = (int)min<int64_t>(64, pm.n - src.m0);
+    src.inv_nv = __builtin_amdgcn_rcpf((float)src.nv);
     src.k0 = chunk * kPoolS;
     src.dir_mode = c.dir_mode;
     src.tmin_scale = c.tmin_scale;
@@ -364,6 +383,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool_list(
     src.ids = ids;
     src.id_offset = id_offset;
     src.base = base;
+    src.inv_k = 1.0 / (double)K;
     int64_t cn = 0, cl = 0, ch = 0;
     drain_pool<false>(nodes4, rec, c, n, pool_n, src, stk + threadIdx.x, fifo + threadIdx.x, tbuf[wv], cn, cl, ch);
     for (int j = lane; j < pool_n; j += 64) {
@@ -447,6 +467,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_sh(const float4 *__restri
     src.dirs = dirs;
     src.m0 = grp * 64;
     src.nv = (int)min<int64_t>(64, sm.n - src.m0);
+    src.inv_nv = __builtin_amdgcn_rcpf((float)src.nv);
     src.k0 = run * sm.chunks_per_run * kPoolS;
     src.dir_mode = c.dir_mode;
     src.tmin_scale = c.tmin_scale;
@@ -682,6 +703,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     src.dirs = dirs;
     src.m0 = grp * 64;
     src.nv = (int)min<int64_t>(64, pm.n - src.m0);
+    src.inv_nv = __builtin_amdgcn_rcpf((float)src.nv);
     src.k0 = chunk * kPoolS;
     src.dir_mode = c.dir_mode;
     src.tmin_scale = c.tmin_scale;

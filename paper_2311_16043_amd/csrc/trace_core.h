@@ -40,7 +40,7 @@ inline Cuts make_cuts(const rv_trace_params &p) {
 // "Building an Orthonormal Basis, Revisited" (JCGT 2017).
 __device__ __forceinline__ void onb_duff(f3 n, f3 &b1, f3 &b2) {
     const float sign = copysignf(1.0f, n.z);
-    const float a = -1.0f / (sign + n.z);
+    const float a = -__builtin_amdgcn_rcpf(sign + n.z);  // |sign + n.z| in [1, 2]; one ulp
     const float b = n.x * n.y * a;
     b1 = mk(1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x);
     b2 = mk(b, sign + n.y * n.y * a, -n.y);
@@ -50,29 +50,37 @@ __device__ __forceinline__ void onb_duff(f3 n, f3 &b1, f3 &b2) {
 __device__ __forceinline__ f3 ray_direction(const float *__restrict__ dirs, int k, int mode, f3 n, f3 b1, f3 b2) {
     const float dx = dirs[3 * k], dy = dirs[3 * k + 1], dz = dirs[3 * k + 2];
     f3 d = mode ? (dx * b1 + dy * b2 + dz * n) : mk(dx, dy, dz);
-    const float inv = 1.0f / sqrtf(dot(d, d));
+    const float inv = __builtin_amdgcn_rsqf(dot(d, d));  // one ulp; |d| is 1 up to rounding
     return inv * d;
 }
 
-// Reciprocal direction with zero components replaced by a tiny signed value.
+// Reciprocal direction (hardware reciprocal, within one ulp) with zero
+// components replaced by a tiny signed value, so every component is finite,
+// nonzero and carries the sign of d.
 __device__ __forceinline__ f3 safe_inv(f3 d) {
     auto r = [](float x) {
         const float tiny = 1e-30f;
         float y = fabsf(x) < tiny ? copysignf(tiny, x) : x;
-        return 1.0f / y;
+        return __builtin_amdgcn_rcpf(y);
     };
     return mk(r(d.x), r(d.y), r(d.z));
 }
 
 // Children of compressed four-wide node `node` whose boxes the ray segment
 // [t0, inf) enters, in slot order; missed and unused slots come out as
-// kEmptyChild. A box plane is O_a + q step_a (q one byte), so its ray
-// distance is fma(q, step_a / d_a, (O_a - o_a) / d_a). step_a / d_a is exact;
-// the roundings of 1/d, of (O_a - o_a) / d_a and of the fma move a plane by at
-// most 2^-23 (|P - o| + |O - o|) <= 2^-21 max|coordinate| in space, which is
-// below the outward margin eta >= 2^-20 (max|coordinate| + 1) that the builder
-// added to every plane. So a box the exact ray enters beyond t0 is never
-// rejected, and no further enlargement of the exit distance is needed.
+// kEmptyChild. A box plane is P = O_a + q step_a (q one byte), so its ray
+// distance is fma(q, step_a inv_a, (O_a - o_a) inv_a) with inv_a the
+// reciprocal of d_a to within one ulp; step_a inv_a is exact (a power-of-two
+// scaling). The roundings of inv_a (2^-23 relative), of O_a - o_a, of the
+// product and of the fma (2^-24 each) move a plane by at most
+// 2^-23 (1.5 |P - o| + |O - o|) <= 5 2^-23 max|coordinate| in space, which
+// is below the outward margin eta >= 2^-20 (max|coordinate| + 1) that the
+// builder added to every plane. So a box the exact ray enters beyond t0 is
+// never rejected, and no further enlargement of the exit distance is needed.
+// The fma is monotone in q, rising for inv_a > 0 and falling for inv_a < 0,
+// so the entry plane of each axis is the low one for a positive direction
+// component and the high one otherwise: the plane bytes are swapped once per
+// node by the direction's signs instead of ordering every pair of distances.
 __device__ __forceinline__ void visit4(const float4 *__restrict__ nodes4, int32_t node, f3 o, f3 inv, float t0,
                                        int32_t (&id)[4]) {
     const uint4 *r = reinterpret_cast<const uint4 *>(nodes4) + 4 * (int64_t)node;
@@ -84,16 +92,21 @@ __device__ __forceinline__ void visit4(const float4 *__restrict__ nodes4, int32_
     const float bx = (__uint_as_float(w0.x) - o.x) * inv.x;
     const float by = (__uint_as_float(w0.y) - o.y) * inv.y;
     const float bz = (__uint_as_float(w0.z) - o.z) * inv.z;
+    // all ones where the direction component is negative
+    const uint32_t mx = (uint32_t)(__float_as_int(inv.x) >> 31), my = (uint32_t)(__float_as_int(inv.y) >> 31),
+                   mz = (uint32_t)(__float_as_int(inv.z) >> 31);
+    // entry (near) and exit (far) plane bytes of the four slots per axis
+    const uint32_t nx = (w1.x & ~mx) | (w1.w & mx), fx = (w1.w & ~mx) | (w1.x & mx);
+    const uint32_t ny = (w1.y & ~my) | (w2.x & my), fy = (w2.x & ~my) | (w1.y & my);
+    const uint32_t nz = (w1.z & ~mz) | (w2.y & mz), fz = (w2.y & ~mz) | (w1.z & mz);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         auto q = [j](uint32_t w) { return (float)((w >> (8 * j)) & 0xffu); };
-        const float lx = fmaf(q(w1.x), ax, bx), hx = fmaf(q(w1.w), ax, bx);
-        const float ly = fmaf(q(w1.y), ay, by), hy = fmaf(q(w2.x), ay, by);
-        const float lz = fmaf(q(w1.z), az, bz), hz = fmaf(q(w2.y), az, bz);
-        const float tn = fmaxf(fmaxf(fminf(lx, hx), fminf(ly, hy)), fmaxf(fminf(lz, hz), t0));
-        const float tf = fminf(fminf(fmaxf(lx, hx), fmaxf(ly, hy)), fmaxf(lz, hz));
-        // kind bits: bit 0 slot used, bit 1 leaf (~index)
-        const bool used = (meta >> (24 + 2 * j)) & 1u;
+        const float tn = fmaxf(fmaxf(fmaf(q(nx), ax, bx), fmaf(q(ny), ay, by)), fmaxf(fmaf(q(nz), az, bz), t0));
+        const float tf = fminf(fminf(fmaf(q(fx), ax, bx), fmaf(q(fy), ay, by)), fmaf(q(fz), az, bz));
+        // kind bits: bit 0 slot used, bit 1 leaf (~index); slots 0 and 2
+        // always hold a child (the first child of each side)
+        const bool used = (j & 1) == 0 || ((meta >> (24 + 2 * j)) & 1u);
         const int32_t leaf_mask = -(int32_t)((meta >> (25 + 2 * j)) & 1u);
         const int32_t idx = (int32_t)(j < 2 ? w2.z : w2.w) + (j & 1);
         id[j] = used && tn <= tf ? (idx ^ leaf_mask) : kEmptyChild;
@@ -199,7 +212,6 @@ struct RingStack {
 
     __device__ __forceinline__ void reset() { sp = 0; }
     __device__ __forceinline__ bool empty() const { return sp == 0; }
-    __device__ __forceinline__ bool full() const { return sp >= kMaxStack; }
     __device__ __forceinline__ void push(int32_t x) {
         const int slot = sp & (kRing - 1);
         if (sp >= kRing) spill[sp - kRing] = lds[slot * stride];
