@@ -171,7 +171,10 @@ rv_status rv_bvh_view(const void *bvh, int64_t n, rv_bvh_arrays *out);
 /* Visibility (Sec. 4.1 traversal, Sec. 4.2 pre-computation)                */
 /* ------------------------------------------------------------------------ */
 
-/* Bytes of trace scratch: one FP64 partial sum per (Gaussian, direction chunk). */
+/*
+ * Bytes of trace scratch: 256 bytes of work-queue counters, then room for the
+ * n*K per-ray values (used when the mean is wanted without per-ray output).
+ */
 size_t rv_trace_workspace_bytes(int64_t n, int32_t K);
 
 /*
@@ -179,9 +182,11 @@ size_t rv_trace_workspace_bytes(int64_t n, int32_t K);
  * ([K][3], see dir_mode), after `bvh` was built from the same g. Writes
  * vis_ray[i*K + k] = T of that ray (if vis_ray != NULL) and
  * vis_mean[i] = (1/K) sum_k T (if vis_mean != NULL); at least one of them must
- * be given. vis_mean needs `ws` (256-byte aligned, at least
- * rv_trace_workspace_bytes(n, K) bytes; may be NULL when vis_mean is NULL).
- * Deterministic: the mean adds per-chunk FP64 partial sums in a fixed order.
+ * be given. ws: device scratch, 256-byte aligned, at least
+ * rv_trace_workspace_bytes(n, K) bytes, or 256 bytes when vis_ray is given;
+ * calls that share a ws must not overlap. Deterministic: each ray's T does
+ * not depend on scheduling, and the mean adds the row in FP64 in a fixed
+ * order.
  * Errors: RV_ERR_INVALID_ARG (null g/bvh/dirs/params, K < 1, both outputs
  * NULL, dir_mode 1 with NULL normals, out-of-range parameters, missing or
  * unaligned ws), RV_ERR_WORKSPACE (ws_bytes too small), RV_ERR_HIP.
@@ -224,6 +229,8 @@ rv_status rv_trace_visibility_sh(const void *bvh, const rv_gaussians *g, const f
  * totals[0] = four-wide node visits, totals[1] = leaf records tested,
  * totals[2] = Gaussians included, summed over all n*K rays (int64, overwritten).
  * Used to compute algorithmic bytes; runs a separate instrumented kernel.
+ * ws: at least 256 bytes of device scratch, 256-byte aligned (work-queue
+ * counters). Errors: as rv_trace_visibility.
  */
 rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
                          const rv_trace_params *p, int64_t *totals, void *ws, size_t ws_bytes,

@@ -3,16 +3,17 @@
 // per-Gaussian average over the K directions (the "averaged visibility" of the
 // ablation study, Sec. 5.4).
 //
-// Work mapping. Every kernel drains pools of rays with the lanes of a wave
-// (see the pooled traversal below): the all-ray forward and the adjoint take
-// 64 Gaussians adjacent in Morton (sorted-leaf) order times a chunk of 4
-// consecutive directions per wave, the list kernel 256 consecutive list
-// entries. ~300k small pools at object scale let the hardware dispatcher
-// balance the skewed per-ray work instead of waiting on the slowest Gaussian.
-// Blocks are renumbered so that each XCD (round-robin dispatch) walks a
-// contiguous range of the Morton order and its L2 sees a compact part of the
-// tree. Per-Gaussian sums are FP64 partials per chunk, added in chunk order by
-// a second kernel (deterministic, no atomics).
+// Work mapping. Rays come in pools (see the pooled traversal below): 64
+// Gaussians adjacent in Morton (sorted-leaf) order times a chunk of 4
+// consecutive directions for the all-ray kernels, 256 consecutive entries for
+// the list kernel. The all-ray forward runs a persistent grid that takes pools
+// from eight queues, one per XCD, each a contiguous eighth of the Morton
+// order, so each L2 sees a compact part of the tree; a wave keeps its lanes
+// supplied across pool boundaries, so the skewed per-ray work leaves lanes
+// idle only in a wave's last pool. Each ray writes its own T; per-Gaussian
+// means are FP64 row sums in a fixed order (deterministic, no atomics).
+#include <atomic>
+
 #include "trace_core.h"
 
 namespace rv {
@@ -136,16 +137,47 @@ struct RaySetup {
     int32_t self;       // original index of the source Gaussian
     int32_t self_leaf;  // its sorted leaf position, or -1 if not known
     bool valid;         // false: not a ray of this scene (finishes at once with NaN)
+    int64_t out;        // output position of its T
 };
 
-// Drain a pool of pool_n rays (setup(idx) describes ray idx) with the lanes of
-// one wave, parking each ray's final T in tbuf[idx]. stk and fifo are this
-// lane's columns of the block's LDS stack ring and leaf FIFO.
-template <bool kCount, class Setup>
-__device__ __forceinline__ void drain_pool(const float4 *__restrict__ nodes4, const float4 *__restrict__ rec,
-                                           const Cuts &c, int64_t n, int pool_n, const Setup &setup,
-                                           int32_t *stk, int32_t *my_fifo, float *tbuf, int64_t &cn, int64_t &cl,
-                                           int64_t &ch) {
+// Pools handed to one wave. XcdQueue: the pools [begin, end) of the wave's
+// XCD, taken one at a time through an atomic counter that all waves on that
+// XCD share (the counter starts at zero); every wave keeps taking until the
+// range is spent, so each XCD's waves finish together. RangeQueue: a fixed
+// run of consecutive pools.
+struct XcdQueue {
+    unsigned long long *ctr;
+    int64_t begin, end;
+    // Next pool in p, false once the range is spent. Called by all lanes.
+    __device__ __forceinline__ bool take(int64_t &p) {
+        unsigned long long t = 0;
+        if ((threadIdx.x & 63) == 0) t = atomicAdd(ctr, 1ull);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(t >> 32));
+        p = begin + (int64_t)(((uint64_t)hi << 32) | lo);
+        return p < end;
+    }
+};
+
+struct RangeQueue {
+    int64_t next, end;
+    __device__ __forceinline__ bool take(int64_t &p) {
+        p = next++;
+        return p < end;
+    }
+};
+
+// Trace the rays of the pools the queue hands out with the lanes of one
+// wave. A lane without a ray takes the next ray of the current pool; when the
+// pool is spent the wave takes the next pool at once, so lanes stay supplied
+// across pool boundaries and only idle in the wave's last pool. A finished
+// ray writes its T to out[r.out] (when out is given). stk and my_fifo are
+// this lane's columns of the block's LDS stack ring and leaf FIFO.
+template <bool kCount, class Queue, class Pools>
+__device__ __forceinline__ void stream_rays(const float4 *__restrict__ nodes4, const float4 *__restrict__ rec,
+                                            const Cuts &c, int64_t n, Queue &queue, Pools &pools,
+                                            int32_t *stk, int32_t *my_fifo, float *__restrict__ out, int64_t &cn,
+                                            int64_t &cl, int64_t &ch) {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = (1ull << lane) - 1ull;
     RingStack<kPoolRing> st;
@@ -156,21 +188,30 @@ __device__ __forceinline__ void drain_pool(const float4 *__restrict__ nodes4, co
     st.sp = 0;
     int fhead = 0, fcount = 0;
     bool has = false;
-    int slot = 0;  // pool index of the current ray
+    int64_t dst = 0;  // output position of the current ray
     f3 o = mk(0.f, 0.f, 0.f), d = o, inv = o;
     float tmin = 0.f, T = 1.f;
     int32_t self = -1, self_leaf = -1, node = -1;
     int64_t budget = 0;
     NoHit none;
-    int next = 0;  // wave-uniform
+    // wave-uniform pool state
+    int next = 0, pool_n = 0;
+    bool more = true;
 
     while (true) {
-        // refill idle lanes from the pool
-        const uint64_t need = __ballot(!has);
-        if (need != 0 && next < pool_n) {
+        // refill idle lanes, moving on to further pools while lanes are idle
+        uint64_t need = __ballot(!has);
+        while (need != 0 && more) {
+            if (next >= pool_n) {
+                int64_t p;
+                more = queue.take(p);
+                pool_n = more ? pools.open(p) : 0;
+                next = 0;
+                continue;
+            }
             const int idx = next + __popcll(need & lt);
             if (!has && idx < pool_n) {
-                const RaySetup r = setup(idx);
+                const RaySetup r = pools(idx);
                 o = r.o;
                 d = r.d;
                 inv = safe_inv(d);
@@ -183,12 +224,13 @@ __device__ __forceinline__ void drain_pool(const float4 *__restrict__ nodes4, co
                 fcount = 0;
                 node = r.valid && n > 1 ? 0 : -1;
                 budget = n;
-                slot = idx;
+                dst = r.out;
                 has = true;
             }
             next += __popcll(need);
+            need = __ballot(!has);
         }
-        if (__ballot(has) == 0) break;
+        if (__ballot(has) == 0) break;  // queue spent, every ray finished
 
         // node phase: one four-wide node per lane with traversal work and FIFO
         // room for all four children
@@ -215,20 +257,17 @@ __device__ __forceinline__ void drain_pool(const float4 *__restrict__ nodes4, co
             }
         }
 
-        // finished rays park their T in the wave's pool buffer
         if (has && node < 0 && fcount == 0) {
-            tbuf[slot] = T;
+            if (out) out[dst] = T;
             has = false;
         }
     }
-    // every lane has left the loop: the pool buffer is complete
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
 }
 
 // Rays of the all-ray kernel: Gaussians m0 .. m0 + nv - 1 (sorted order) times
 // directions k0 .. k0 + s - 1; pool index idx = j * nv + (m - m0). Origin data
-// come from the prepared per-leaf records.
+// come from the prepared per-leaf records. The output position of ray
+// (i, k) is i * K + k with i the Gaussian's original index.
 struct GridSource {
     const float4 *rec, *origins;
     const float *dirs;
@@ -236,6 +275,7 @@ struct GridSource {
     int nv, k0, dir_mode;
     float tmin_scale;
     float inv_nv;  // reciprocal of nv (within one ulp)
+    int K = 0;
     __device__ __forceinline__ RaySetup operator()(int idx) const {
         // idx / nv from the float quotient: (idx + 1/2) / nv lies at least
         // 1/(2 nv) >= 1/128 from an integer, far beyond its rounding error
@@ -255,7 +295,25 @@ struct GridSource {
         r.self = __float_as_int(rec[kLeafF4 * m + 2].w);
         r.self_leaf = (int32_t)m;
         r.valid = true;
+        r.out = (int64_t)r.self * K + k0 + j;
         return r;
+    }
+};
+
+// All-ray pools: pool p = group * n_chunks + chunk covers the 64 Gaussians
+// of the group (sorted order) times the chunk's kPoolS directions.
+struct GridPools : GridSource {
+    int64_t n;
+    int n_chunks;
+    // Make pool p current; returns its number of rays.
+    __device__ __forceinline__ int open(int64_t p) {
+        const int64_t grp = p / n_chunks;
+        const int chunk = (int)(p - grp * n_chunks);
+        m0 = grp * 64;
+        nv = (int)min<int64_t>(64, n - m0);
+        inv_nv = __builtin_amdgcn_rcpf((float)nv);
+        k0 = chunk * kPoolS;
+        return nv * min(kPoolS, K - k0);
     }
 };
 
@@ -270,9 +328,12 @@ struct ListSource {
     const int64_t *ids;
     int64_t id_offset, base;
     double inv_k;  // 1 / K
+    bool out_by_value;
     __device__ __forceinline__ RaySetup operator()(int idx) const {
         RaySetup r;
-        const int64_t rid = ids[base + idx] + id_offset;
+        const int64_t entry = ids[base + idx];
+        const int64_t rid = entry + id_offset;
+        r.out = out_by_value ? entry : base + idx;
         r.valid = rid >= 0 && rid < n * (int64_t)K;
         // rid / K from the FP64 quotient (off by at most one for rid < 2^52,
         // where rid converts exactly), corrected so that 0 <= k < K; integer
@@ -306,46 +367,50 @@ struct ListSource {
     }
 };
 
+// List pools: pool p covers list entries p * kPoolS * 64 onwards.
+struct ListPools : ListSource {
+    int64_t total;
+    __device__ __forceinline__ int open(int64_t p) {
+        base = p * (kPoolS * 64);
+        return (int)min<int64_t>(kPoolS * 64, total - base);
+    }
+};
+
+// All n K rays through per-XCD queues of pools. The grid is persistent (a
+// multiple of 8 blocks, about what the device holds at once) and block b
+// serves the queue of XCD b % 8 (round-robin dispatch), whose range is a
+// contiguous eighth of the pools: each L2 sees a compact part of the tree.
 template <bool kCount>
-__global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__restrict__ nodes4,
-                                                            const float4 *__restrict__ rec,
-                                                            const float4 *__restrict__ origins,
-                                                            const float *__restrict__ dirs, PoolMap pm, Cuts c,
-                                                            float *__restrict__ vis_ray, double *__restrict__ partial,
-                                                            unsigned long long *__restrict__ totals) {
+__global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__restrict__ nodes4,
+                                                              const float4 *__restrict__ rec,
+                                                              const float4 *__restrict__ origins,
+                                                              const float *__restrict__ dirs, int64_t n, int K,
+                                                              Cuts c, unsigned long long *__restrict__ queues,
+                                                              float *__restrict__ vis_ray,
+                                                              unsigned long long *__restrict__ totals) {
     __shared__ int32_t stk[kPoolRing * kTraceBlock];
     __shared__ int32_t fifo[kFifo * kTraceBlock];
-    __shared__ float tbuf[kWavesPerBlock][kPoolS * 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t w = pm.w_off + xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
-    if (w >= pm.n_items) return;  // wave-uniform
-    const int64_t grp = w / pm.n_chunks;
-    const int chunk = (int)(w - grp * pm.n_chunks);
-    GridSource src;
-    src.rec = rec;
-    src.origins = origins;
-    src.dirs = dirs;
-    src.m0 = grp * 64;
-    src.nv = (int)min<int64_t>(64, pm.n - src.m0);
-    src.inv_nv = __builtin_amdgcn_rcpf((float)src.nv);
-    src.k0 = chunk * kPoolS;
-    src.dir_mode = c.dir_mode;
-    src.tmin_scale = c.tmin_scale;
-    const int s_eff = min(kPoolS, pm.K - src.k0);
+    const int x = (int)(blockIdx.x % kXcds);
+    GridPools pools;
+    pools.rec = rec;
+    pools.origins = origins;
+    pools.dirs = dirs;
+    pools.dir_mode = c.dir_mode;
+    pools.tmin_scale = c.tmin_scale;
+    pools.K = K;
+    pools.n = n;
+    pools.n_chunks = (K + kPoolS - 1) / kPoolS;
+    pools.m0 = 0;
+    pools.nv = 1;
+    pools.k0 = 0;
+    pools.inv_nv = 1.0f;
+    const int64_t n_pools = ((n + 63) / 64) * (int64_t)pools.n_chunks;
+    XcdQueue q;
+    q.ctr = queues + x;
+    q.begin = n_pools * x / kXcds;
+    q.end = n_pools * (x + 1) / kXcds;
     int64_t cn = 0, cl = 0, ch = 0;
-    drain_pool<kCount>(nodes4, rec, c, pm.n, src.nv * s_eff, src, stk + threadIdx.x, fifo + threadIdx.x, tbuf[wv],
-                       cn, cl, ch);
-    if (lane < src.nv) {
-        const int64_t m = src.m0 + lane;
-        const int32_t self = __float_as_int(rec[kLeafF4 * m + 2].w);
-        double sum = 0.0;
-        for (int j = 0; j < s_eff; ++j) {
-            const float t = tbuf[wv][j * src.nv + lane];
-            if (vis_ray) vis_ray[(int64_t)self * pm.K + src.k0 + j] = t;
-            sum += (double)t;
-        }
-        if (partial) partial[(int64_t)chunk * pm.n + self] = sum;
-    }
+    stream_rays<kCount>(nodes4, rec, c, n, q, pools, stk + threadIdx.x, fifo + threadIdx.x, vis_ray, cn, cl, ch);
     if (kCount) {
         atomicAdd(totals + 0, (unsigned long long)cn);
         atomicAdd(totals + 1, (unsigned long long)cl);
@@ -353,42 +418,57 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_pool(const float4 *__rest
     }
 }
 
-// Listed rays, kPoolS * 64 list entries per wave. The list holds
-// *count entries when count is given (read on the device), else n_list.
-// out_by_value: T goes to out[ids[j]] (the list holds output positions, the
-// ray being id_offset + ids[j]); otherwise to out[j].
-__global__ __launch_bounds__(kTraceBlock) void k_trace_pool_list(
+// Listed rays: wave w takes the run of pools [w R, (w + 1) R) of kPoolS * 64
+// list entries each. The list holds *count entries when count is given (read
+// on the device), else n_list. out_by_value: T goes to out[ids[j]] (the list
+// holds output positions, the ray being id_offset + ids[j]); otherwise to
+// out[j].
+__global__ __launch_bounds__(kTraceBlock) void k_trace_list(
     const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float *__restrict__ mean,
     const float *__restrict__ normal, const float *__restrict__ log_scale, int64_t n, const float *__restrict__ dirs,
     int K, Cuts c, const int64_t *__restrict__ ids, int64_t n_list, const unsigned long long *__restrict__ count,
-    int64_t id_offset, int out_by_value, float *__restrict__ out) {
+    int64_t id_offset, int out_by_value, int64_t run, float *__restrict__ out) {
     __shared__ int32_t stk[kPoolRing * kTraceBlock];
     __shared__ int32_t fifo[kFifo * kTraceBlock];
-    __shared__ float tbuf[kWavesPerBlock][kPoolS * 64];
     constexpr int kPool = kPoolS * 64;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t total = count ? min<int64_t>(n_list, (int64_t)*count) : n_list;
-    const int64_t base = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * kPool;
-    if (base >= total) return;  // wave-uniform
-    const int pool_n = (int)min<int64_t>(kPool, total - base);
-    ListSource src;
-    src.mean = mean;
-    src.normal = normal;
-    src.log_scale = log_scale;
-    src.dirs = dirs;
-    src.n = n;
-    src.K = K;
-    src.dir_mode = c.dir_mode;
-    src.tmin_scale = c.tmin_scale;
-    src.ids = ids;
-    src.id_offset = id_offset;
-    src.base = base;
-    src.inv_k = 1.0 / (double)K;
+    const int64_t n_pools = (total + kPool - 1) / kPool;
+    RangeQueue q;
+    q.next = w * run;
+    q.end = min(n_pools, q.next + run);
+    if (q.next >= q.end) return;  // wave-uniform
+    ListPools pools;
+    pools.mean = mean;
+    pools.normal = normal;
+    pools.log_scale = log_scale;
+    pools.dirs = dirs;
+    pools.n = n;
+    pools.K = K;
+    pools.dir_mode = c.dir_mode;
+    pools.tmin_scale = c.tmin_scale;
+    pools.ids = ids;
+    pools.id_offset = id_offset;
+    pools.base = 0;
+    pools.inv_k = 1.0 / (double)K;
+    pools.out_by_value = out_by_value != 0;
+    pools.total = total;
     int64_t cn = 0, cl = 0, ch = 0;
-    drain_pool<false>(nodes4, rec, c, n, pool_n, src, stk + threadIdx.x, fifo + threadIdx.x, tbuf[wv], cn, cl, ch);
-    for (int j = lane; j < pool_n; j += 64) {
-        const int64_t dst = out_by_value ? ids[base + j] : base + j;
-        out[dst] = tbuf[wv][j];
+    stream_rays<false>(nodes4, rec, c, n, q, pools, stk + threadIdx.x, fifo + threadIdx.x, out, cn, cl, ch);
+}
+
+// vis_mean[i] = (1/K) sum_k vis[i K + k]: one wave per Gaussian, FP64 lane
+// sums over a fixed stride and a fixed butterfly (deterministic).
+__global__ __launch_bounds__(256) void k_mean_rows(const float *__restrict__ vis, int64_t n, int K,
+                                                   float *__restrict__ vis_mean) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+        const float *row = vis + i * K;
+        double s = 0.0;
+        for (int k = lane; k < K; k += 64) s += (double)row[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) vis_mean[i] = (float)(s / (double)K);
     }
 }
 
@@ -599,16 +679,6 @@ __global__ __launch_bounds__(256) void k_sh_from_partials(const double *__restri
 #pragma unroll
     for (int q = 0; q < kShCoef; ++q) vis_sh[i * kShCoef + q] = (float)(s[q] * dw);
     if (vis_mean) vis_mean[i] = (float)(s[kShCoef] / (double)K);
-}
-
-// vis_mean[i] = (sum over chunks, in chunk order, of the FP64 partials) / K.
-__global__ __launch_bounds__(256) void k_mean_from_partials(const double *__restrict__ partial, int64_t n,
-                                                            int n_chunks, int K, float *__restrict__ vis_mean) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int c = 0; c < n_chunks; ++c) s += partial[(int64_t)c * n + i];
-    vis_mean[i] = (float)(s / (double)K);
 }
 
 // ---- adjoint ----------------------------------------------------------------
@@ -861,6 +931,37 @@ rv_status validate_trace(const char *fn, const void *bvh, const rv_gaussians *g,
     return RV_OK;
 }
 
+
+// Blocks of a persistent traversal grid: what the device holds at once
+// (a multiple of 8, at least 8: every XCD queue has blocks), no more than the
+// pools need.
+int64_t stream_blocks(int64_t n_pools) {
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    int nb = (dev >= 0 && dev < 64) ? cached[dev].load() : 0;
+    if (nb <= 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev < 0 ? 0 : dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_stream<false>, kTraceBlock, 0) !=
+                hipSuccess ||
+            per_cu <= 0)
+            per_cu = 4;
+        (void)hipGetLastError();  // a failed query above must not surface as a launch error
+        nb = cus * per_cu;
+        if (dev >= 0 && dev < 64) cached[dev].store(nb);
+    }
+    int64_t want = std::min<int64_t>(nb, (n_pools + kWavesPerBlock - 1) / kWavesPerBlock);
+    want = (want + kXcds - 1) / kXcds * kXcds;
+    return std::max<int64_t>(want, kXcds);
+}
+
+// Waves of the list kernel beyond which each wave takes a run of several
+// pools (about four times what the device holds at once).
+constexpr int64_t kListTargetWaves = 32768;
+
 }  // namespace
 
 void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs, int K, const Cuts &c,
@@ -868,11 +969,13 @@ void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs
                        bool out_by_value, float *out, hipStream_t stream) {
     if (n_list <= 0) return;
     const BvhLayout L = bvh_layout(g->n);
-    const int64_t waves = (n_list + kPoolS * 64 - 1) / (kPoolS * 64);
-    hipLaunchKernelGGL(k_trace_pool_list, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
+    const int64_t pools = (n_list + kPoolS * 64 - 1) / (kPoolS * 64);
+    const int64_t run = (pools + kListTargetWaves - 1) / kListTargetWaves;
+    const int64_t waves = (pools + run - 1) / run;
+    hipLaunchKernelGGL(k_trace_list, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
                        dim3(kTraceBlock), 0, stream, at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean,
                        c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, c, ids, n_list, count, id_offset,
-                       out_by_value ? 1 : 0, out);
+                       out_by_value ? 1 : 0, run, out);
 }
 
 }  // namespace rv
@@ -881,9 +984,28 @@ using namespace rv;
 
 extern "C" size_t rv_trace_workspace_bytes(int64_t n, int32_t K) {
     if (n < 1 || K < 1) return kAlign;
-    const PoolMap pm = make_pool(n, K);
-    return align_up((size_t)pm.n_chunks * (size_t)n * sizeof(double)) + kAlign;
+    return kAlign + align_up((size_t)n * (size_t)K * sizeof(float));
 }
+
+namespace {
+
+// The persistent all-ray traversal: clear the XCD queues (first 64 bytes of
+// ws), then trace every ray (writing vis_ray when given, counters into totals
+// when counting).
+template <bool kCount>
+void launch_trace_stream(const void *bvh, const rv_gaussians *g, const float *dirs, int K, const Cuts &c,
+                         void *ws, float *vis_ray, unsigned long long *totals, hipStream_t s) {
+    const BvhLayout L = bvh_layout(g->n);
+    const int64_t n_pools = ((g->n + 63) / 64) * (int64_t)((K + kPoolS - 1) / kPoolS);
+    auto *queues = static_cast<unsigned long long *>(ws);
+    hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(queues),
+                       (int64_t)(2 * kXcds), 0u);
+    hipLaunchKernelGGL(k_trace_stream<kCount>, dim3((unsigned)stream_blocks(n_pools)), dim3(kTraceBlock), 0, s,
+                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, g->n,
+                       K, c, queues, vis_ray, totals);
+}
+
+}  // namespace
 
 extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
                                          const rv_trace_params *p, float *vis_ray, float *vis_mean, void *ws,
@@ -892,29 +1014,18 @@ extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g,
     rv_status st = validate_trace("rv_trace_visibility", bvh, g, dirs, K, p);
     if (st != RV_OK) return st;
     RV_REQUIRE(vis_ray || vis_mean, RV_ERR_INVALID_ARG, "rv_trace_visibility: both outputs are NULL");
-    const PoolMap pm = make_pool(g->n, K);
-    double *partial = nullptr;
-    if (vis_mean) {
-        RV_REQUIRE(ws && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG,
-                   "rv_trace_visibility: vis_mean needs a 256-byte aligned workspace");
-        RV_REQUIRE(ws_bytes >= rv_trace_workspace_bytes(g->n, K), RV_ERR_WORKSPACE,
-                   "rv_trace_visibility: ws_bytes %zu < %zu", ws_bytes, rv_trace_workspace_bytes(g->n, K));
-        partial = static_cast<double *>(ws);
-    }
-    const BvhLayout L = bvh_layout(g->n);
-    const Cuts c = make_cuts(*p);
+    RV_REQUIRE(ws && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG,
+               "rv_trace_visibility: needs a 256-byte aligned workspace");
+    const size_t need = vis_ray ? kAlign : rv_trace_workspace_bytes(g->n, K);
+    RV_REQUIRE(ws_bytes >= need, RV_ERR_WORKSPACE, "rv_trace_visibility: ws_bytes %zu < %zu", ws_bytes, need);
+    // the per-ray values go to vis_ray, else to the workspace after the queues
+    float *rays = vis_ray ? vis_ray : reinterpret_cast<float *>(static_cast<char *>(ws) + kAlign);
     hipStream_t s = (hipStream_t)stream;
-    for (int64_t w0 = 0; w0 < pm.n_items; w0 += kLaunchWaves) {
-        PoolMap part = pm;
-        part.w_off = w0;
-        const int64_t nb = (std::min(kLaunchWaves, pm.n_items - w0) + kWavesPerBlock - 1) / kWavesPerBlock;
-        hipLaunchKernelGGL(k_trace_pool<false>, dim3((unsigned)nb), dim3(kTraceBlock), 0, s, at<float4>(bvh, L.nodes4),
-                           at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, part, c, vis_ray, partial,
-                           (unsigned long long *)nullptr);
+    launch_trace_stream<false>(bvh, g, dirs, K, make_cuts(*p), ws, rays, nullptr, s);
+    if (vis_mean) {
+        const int64_t blocks = std::min<int64_t>((g->n + 3) / 4, int64_t(1) << 20);
+        hipLaunchKernelGGL(k_mean_rows, dim3((unsigned)blocks), dim3(256), 0, s, rays, g->n, K, vis_mean);
     }
-    if (vis_mean)
-        hipLaunchKernelGGL(k_mean_from_partials, dim3(grid_for(g->n, 256)), dim3(256), 0, s, partial, g->n,
-                           pm.n_chunks, K, vis_mean);
     return check_launch("rv_trace_visibility");
 }
 
@@ -925,22 +1036,13 @@ extern "C" rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, cons
     rv_status st = validate_trace("rv_trace_stats", bvh, g, dirs, K, p);
     if (st != RV_OK) return st;
     RV_REQUIRE(totals, RV_ERR_INVALID_ARG, "rv_trace_stats: null totals");
-    (void)ws;
-    (void)ws_bytes;
-    const PoolMap pm = make_pool(g->n, K);
-    const BvhLayout L = bvh_layout(g->n);
-    const Cuts c = make_cuts(*p);
+    RV_REQUIRE(ws && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG,
+               "rv_trace_stats: needs a 256-byte aligned workspace");
+    RV_REQUIRE(ws_bytes >= kAlign, RV_ERR_WORKSPACE, "rv_trace_stats: ws_bytes %zu < %zu", ws_bytes, kAlign);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(totals), (int64_t)6,
                        0u);
-    for (int64_t w0 = 0; w0 < pm.n_items; w0 += kLaunchWaves) {
-        PoolMap part = pm;
-        part.w_off = w0;
-        const int64_t nb = (std::min(kLaunchWaves, pm.n_items - w0) + kWavesPerBlock - 1) / kWavesPerBlock;
-        hipLaunchKernelGGL(k_trace_pool<true>, dim3((unsigned)nb), dim3(kTraceBlock), 0, s, at<float4>(bvh, L.nodes4),
-                           at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, part, c, (float *)nullptr,
-                           (double *)nullptr, (unsigned long long *)totals);
-    }
+    launch_trace_stream<true>(bvh, g, dirs, K, make_cuts(*p), ws, nullptr, (unsigned long long *)totals, s);
     return check_launch("rv_trace_stats");
 }
 

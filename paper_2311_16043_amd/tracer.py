@@ -170,7 +170,8 @@ def trace_visibility(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = 
     K = int(d.shape[0])
     vr = (out_ray if out_ray is not None else torch.empty((g.n, K), dtype=_F32, device=dev)) if want_ray else None
     vm = (out_mean if out_mean is not None else torch.empty((g.n,), dtype=_F32, device=dev)) if want_mean else None
-    ws_bytes = _lib.load().rv_trace_workspace_bytes(g.n, K)
+    # 256 bytes of queue counters suffice when the per-ray values go to vr
+    ws_bytes = 256 if vr is not None else _lib.load().rv_trace_workspace_bytes(g.n, K)
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = _alloc_bytes(ws_bytes, dev)
     gc, pc = g.c(), params.c()
@@ -218,9 +219,10 @@ def trace_stats(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = None)
     dev = g.mean.device
     d = _dirs(dirs, dev)
     tot = torch.zeros(3, dtype=torch.int64, device=dev)
+    ws = _alloc_bytes(256, dev)
     gc, pc = g.c(), params.c()
     _lib.call("rv_trace_stats", bvh.ptr, C.byref(gc), d.data_ptr(), int(d.shape[0]), C.byref(pc), tot.data_ptr(),
-              None, 0, _stream_ptr(dev))
+              ws.data_ptr(), ws.numel(), _stream_ptr(dev))
     t = tot.cpu().tolist()
     return dict(nodes=t[0], leaves=t[1], hits=t[2])
 

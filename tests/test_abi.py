@@ -96,7 +96,8 @@ def test_trace_rejects_bad_params(lib, bad):
     P = 1 << 40
     g = _g()
     p = _params(**bad)
-    assert lib.rv_trace_visibility(P, C.byref(g), P, 8, C.byref(p), P, P, None, 0, None) == _lib.RV_ERR_INVALID_ARG
+    ws = lib.rv_trace_workspace_bytes(10, 8)
+    assert lib.rv_trace_visibility(P, C.byref(g), P, 8, C.byref(p), P, P, P, ws, None) == _lib.RV_ERR_INVALID_ARG
     assert lib.rv_last_error()
 
 
@@ -105,18 +106,27 @@ def test_trace_rejects_bad_arguments(lib):
     g = _g()
     p = _params()
     f = lib.rv_trace_visibility
-    assert f(P, C.byref(g), P, 0, C.byref(p), P, P, None, 0, None) == _lib.RV_ERR_INVALID_ARG  # K = 0
-    assert f(P, C.byref(g), P, 8, C.byref(p), None, None, None, 0, None) == _lib.RV_ERR_INVALID_ARG  # no output
-    assert f(None, C.byref(g), P, 8, C.byref(p), P, P, None, 0, None) == _lib.RV_ERR_INVALID_ARG
+    ws = lib.rv_trace_workspace_bytes(10, 8)
+    assert ws >= 256 + 10 * 8 * 4 and ws % 256 == 0
+    assert f(P, C.byref(g), P, 0, C.byref(p), P, P, P, ws, None) == _lib.RV_ERR_INVALID_ARG  # K = 0
+    assert f(P, C.byref(g), P, 8, C.byref(p), None, None, P, ws, None) == _lib.RV_ERR_INVALID_ARG  # no output
+    assert f(None, C.byref(g), P, 8, C.byref(p), P, P, P, ws, None) == _lib.RV_ERR_INVALID_ARG
     gn = _g(normal=False)
-    assert f(P, C.byref(gn), P, 8, C.byref(p), P, P, None, 0, None) == _lib.RV_ERR_INVALID_ARG  # hemisphere, no normal
+    assert f(P, C.byref(gn), P, 8, C.byref(p), P, P, P, ws, None) == _lib.RV_ERR_INVALID_ARG  # hemisphere, no normal
+    # the workspace: always needed (queue counters), 256 bytes with per-ray output, the full size without
+    assert f(P, C.byref(g), P, 8, C.byref(p), P, P, None, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert f(P, C.byref(g), P, 8, C.byref(p), P, P, P + 64, ws, None) == _lib.RV_ERR_INVALID_ARG
+    assert f(P, C.byref(g), P, 8, C.byref(p), P, P, P, 255, None) == _lib.RV_ERR_WORKSPACE
+    assert f(P, C.byref(g), P, 8, C.byref(p), None, P, P, ws - 256, None) == _lib.RV_ERR_WORKSPACE
     assert lib.rv_trace_rays(P, C.byref(g), P, 8, C.byref(p), P, -1, P, None) == _lib.RV_ERR_INVALID_ARG
     assert lib.rv_trace_rays(P, C.byref(g), P, 8, C.byref(p), None, 0, None, None) == 0  # empty list: no-op
     assert lib.rv_trace_visibility_backward(P, C.byref(g), P, 8, C.byref(p), None, None, None, P, P, P,
                                             None) == _lib.RV_ERR_INVALID_ARG
     assert lib.rv_trace_visibility_backward(P, C.byref(g), P, 8, C.byref(p), P, None, None, None, P, P,
                                             None) == _lib.RV_ERR_INVALID_ARG
-    assert lib.rv_trace_stats(P, C.byref(g), P, 8, C.byref(p), None, None, 0, None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_trace_stats(P, C.byref(g), P, 8, C.byref(p), None, P, 256, None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_trace_stats(P, C.byref(g), P, 8, C.byref(p), P, None, 0, None) == _lib.RV_ERR_INVALID_ARG
+    assert lib.rv_trace_stats(P, C.byref(g), P, 8, C.byref(p), P, P, 128, None) == _lib.RV_ERR_WORKSPACE
 
 
 def test_refit_rejects_bad_arguments(lib):
