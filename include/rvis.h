@@ -323,7 +323,7 @@ rv_status rv_surrogate_view(const void *params, rv_surrogate_arrays *out);
 /* Bytes of training scratch for batches of up to `batch` samples. */
 size_t rv_surrogate_train_workspace_bytes(int32_t batch);
 
-/* Bytes of inference scratch for q_count grid queries (fallback list). */
+/* Bytes of inference scratch for q_count grid queries (counters, fallback list and flags). */
 size_t rv_surrogate_infer_workspace_bytes(int64_t q_count);
 
 /*
@@ -362,8 +362,12 @@ rv_status rv_surrogate_infer_xd(const void *params, const float *x, const float 
  * forms it). vis[s] receives the surrogate's V, or the tracer's T where the
  * predicted error U exceeds tau and `bvh` is not NULL (fallback; the same bits
  * as rv_trace_rays for that ray). unc (may be NULL) receives U; *n_fallback
- * (device int64) the number of traced queries. Queries are compacted with
- * wave ballots into a list in `ws` and traced by a persistent kernel.
+ * (device int64) the number of traced queries. Queries are flagged, gathered
+ * into a list in `ws` in the BVH's leaf (Morton) order of their Gaussians,
+ * and traced by a persistent kernel; ws: 256-byte aligned,
+ * rv_surrogate_infer_workspace_bytes(q_count) bytes, not shared by
+ * overlapping calls. Deterministic (each query's value does not depend on
+ * the list order).
  */
 rv_status rv_surrogate_infer(const void *params, const void *bvh, const rv_gaussians *g, const float *dirs,
                              int32_t K, const rv_trace_params *p, int64_t q_begin, int64_t q_count, float tau,

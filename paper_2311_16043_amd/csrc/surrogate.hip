@@ -130,8 +130,7 @@ struct FwdArgs {
     int K, dir_mode;
     int64_t q_begin;
     float tau;
-    int64_t *fb_list;
-    unsigned long long *fb_count;
+    uint8_t *fb_flag;  // per query: 1 = to be traced (grid mode with a BVH), else NULL
 };
 
 // feature-major activation sections: HT0 (64 rows), HT1..HT4 (256 rows each)
@@ -296,19 +295,10 @@ __device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
         const float V = 1.0f / (1.0f + expf(-z0));
         const float U = fmaxf(z1, 0.f) + log1pf(expf(-fabsf(z1)));
         if (kMode != kModeTrain) {
-            const bool fb = g == 0 && valid && a.fb_list && U > a.tau;
             if (g == 0 && valid) {
                 a.vis[s] = V;
                 if (a.unc) a.unc[s] = U;
-            }
-            if (kMode == kModeGrid) {
-                const uint64_t m = __ballot(fb);
-                if (m) {
-                    unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(a.fb_count, (unsigned long long)__popcll(m));
-                    base = __shfl(base, 0);
-                    if (fb) a.fb_list[base + __popcll(m & ((1ull << lane) - 1ull))] = s;
-                }
+                if (kMode == kModeGrid && a.fb_flag) a.fb_flag[s] = U > a.tau ? 1 : 0;
             }
         } else {
             const float T = Tv[nt];
@@ -620,6 +610,44 @@ __global__ void k_store_count(const unsigned long long *__restrict__ count, int6
     if (threadIdx.x == 0) *out = (int64_t)*count;
 }
 
+// Fallback list in the BVH's leaf (Morton) order: one wave per sorted leaf m
+// appends the flagged queries of Gaussian i = src(m) that lie in the range
+// [q_begin, q_begin + q_count), as positions s = q - q_begin in increasing
+// order, after one atomic reservation per Gaussian. Rays of nearby Gaussians
+// then sit together in the list, so the tracer's concurrent pools share the
+// part of the tree in cache. The list order between Gaussians depends on
+// scheduling; each ray's result does not.
+__global__ __launch_bounds__(256) void k_fallback_rows(const float4 *__restrict__ rec, int64_t n, int K,
+                                                       int64_t q_begin, int64_t q_count,
+                                                       const uint8_t *__restrict__ flag,
+                                                       unsigned long long *__restrict__ count,
+                                                       int64_t *__restrict__ list) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int64_t q_end = q_begin + q_count;
+    for (int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); m < n; m += (int64_t)gridDim.x * 4) {
+        const int64_t i = __float_as_int(rec[kLeafF4 * m + 2].w);
+        const int64_t lo = max(i * K, q_begin) - q_begin, hi = min((i + 1) * K, q_end) - q_begin;
+        if (lo >= hi) continue;  // wave-uniform
+        int total = 0;
+        for (int64_t s0 = lo; s0 < hi; s0 += 64) {
+            const int64_t s = s0 + lane;
+            total += __popcll(__ballot(s < hi && flag[s] != 0));
+        }
+        if (total == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count, (unsigned long long)total);
+        base = __shfl(base, 0);
+        for (int64_t s0 = lo; s0 < hi; s0 += 64) {
+            const int64_t s = s0 + lane;
+            const bool f = s < hi && flag[s] != 0;
+            const uint64_t b = __ballot(f);
+            if (f) list[base + __popcll(b & lt)] = s;
+            base += __popcll(b);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_ray_setup(const float *__restrict__ mean, const float *__restrict__ normal,
                                                    int64_t n, const float *__restrict__ dirs, int K, int dir_mode,
                                                    const int64_t *__restrict__ ids, int64_t n_rays,
@@ -746,9 +774,11 @@ extern "C" size_t rv_surrogate_train_workspace_bytes(int32_t batch) {
     return train_ws(batch).total;
 }
 
+// Inference scratch: [0, 256) the fallback count (byte 0) and the tracer's
+// eight queue counters (byte 64); the list of q_count int64; q_count flags.
 extern "C" size_t rv_surrogate_infer_workspace_bytes(int64_t q_count) {
     if (q_count < 0) return 0;
-    return align_up((size_t)q_count * sizeof(int64_t)) + kAlign;
+    return kAlign + align_up((size_t)q_count * sizeof(int64_t)) + align_up((size_t)q_count);
 }
 
 extern "C" rv_status rv_surrogate_init(void *params, uint64_t seed, const float *box_lo_host, const float *box_hi_host,
@@ -874,7 +904,9 @@ extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, con
     const SurLayout L = sur_layout();
     hipStream_t s = (hipStream_t)stream;
     unsigned long long *count = at<unsigned long long>(ws, 0);
+    unsigned long long *queues = at<unsigned long long>(ws, 64);
     int64_t *list = at<int64_t>(ws, kAlign);
+    uint8_t *flag = at<uint8_t>(ws, kAlign + align_up((size_t)q_count * sizeof(int64_t)));
     hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(256), 0, s, reinterpret_cast<float *>(count), (int64_t)2, 0.0f);
     FwdArgs fa{};
     fa.master = at<float>(params, L.master);
@@ -890,8 +922,7 @@ extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, con
     fa.dir_mode = p->dir_mode;
     fa.q_begin = q_begin;
     fa.tau = tau;
-    fa.fb_list = bvh ? list : nullptr;
-    fa.fb_count = count;
+    fa.fb_flag = bvh ? flag : nullptr;
     for (int64_t off = 0; off < q_count; off += kLaunchSamples) {
         fa.s_off = off;
         const int64_t cnt = std::min(kLaunchSamples, q_count - off);
@@ -900,8 +931,12 @@ extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, con
     if (bvh) {
         const Cuts c = make_cuts(*p);
         // the compacted fallback list holds positions s; the ray is q_begin + s
+        const BvhLayout BL = bvh_layout(g->n);
+        const int64_t rows_blocks = std::min<int64_t>((g->n + 3) / 4, int64_t(1) << 16);
+        hipLaunchKernelGGL(k_fallback_rows, dim3((unsigned)rows_blocks), dim3(256), 0, s, at<float4>(bvh, BL.leaf_rec),
+                           g->n, (int)K, q_begin, q_count, flag, count, list);
         launch_trace_list(bvh, g, dirs, K, c, (const int64_t *)list, q_count, (const unsigned long long *)count,
-                          q_begin, true, vis, s);
+                          q_begin, true, vis, queues, s);
         if (n_fallback)
             hipLaunchKernelGGL(k_store_count, dim3(1), dim3(64), 0, s, (const unsigned long long *)count, n_fallback);
     } else if (n_fallback) {

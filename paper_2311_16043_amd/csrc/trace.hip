@@ -13,6 +13,7 @@
 // idle only in a wave's last pool. Each ray writes its own T; per-Gaussian
 // means are FP64 row sums in a fixed order (deterministic, no atomics).
 #include <atomic>
+#include <type_traits>
 
 #include "trace_core.h"
 
@@ -418,26 +419,38 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__re
     }
 }
 
-// Listed rays: wave w takes the run of pools [w R, (w + 1) R) of kPoolS * 64
-// list entries each. The list holds *count entries when count is given (read
-// on the device), else n_list. out_by_value: T goes to out[ids[j]] (the list
-// holds output positions, the ray being id_offset + ids[j]); otherwise to
-// out[j].
+// Listed rays in pools of kPoolS * 64 list entries. The list holds *count
+// entries when count is given (read on the device), else n_list.
+// out_by_value: T goes to out[ids[j]] (the list holds output positions, the
+// ray being id_offset + ids[j]); otherwise to out[j]. With kQueue the grid is
+// persistent and takes pools from per-XCD queues (queues[8], zero at launch),
+// each a contiguous eighth of the list; otherwise wave w takes the run of
+// pools [w R, (w + 1) R).
+template <bool kQueue>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_list(
     const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float *__restrict__ mean,
     const float *__restrict__ normal, const float *__restrict__ log_scale, int64_t n, const float *__restrict__ dirs,
     int K, Cuts c, const int64_t *__restrict__ ids, int64_t n_list, const unsigned long long *__restrict__ count,
-    int64_t id_offset, int out_by_value, int64_t run, float *__restrict__ out) {
+    int64_t id_offset, int out_by_value, int64_t run, unsigned long long *__restrict__ queues,
+    float *__restrict__ out) {
     __shared__ int32_t stk[kPoolRing * kTraceBlock];
     __shared__ int32_t fifo[kFifo * kTraceBlock];
     constexpr int kPool = kPoolS * 64;
-    const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t total = count ? min<int64_t>(n_list, (int64_t)*count) : n_list;
     const int64_t n_pools = (total + kPool - 1) / kPool;
-    RangeQueue q;
-    q.next = w * run;
-    q.end = min(n_pools, q.next + run);
-    if (q.next >= q.end) return;  // wave-uniform
+    using Queue = typename std::conditional<kQueue, XcdQueue, RangeQueue>::type;
+    Queue q;
+    if constexpr (kQueue) {
+        const int x = (int)(blockIdx.x % kXcds);
+        q.ctr = queues + x;
+        q.begin = n_pools * x / kXcds;
+        q.end = n_pools * (x + 1) / kXcds;
+    } else {
+        const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+        q.next = w * run;
+        q.end = min(n_pools, q.next + run);
+        if (q.next >= q.end) return;  // wave-uniform
+    }
     ListPools pools;
     pools.mean = mean;
     pools.normal = normal;
@@ -932,9 +945,16 @@ rv_status validate_trace(const char *fn, const void *bvh, const rv_gaussians *g,
 }
 
 
-// Blocks of a persistent traversal grid: what the device holds at once
-// (a multiple of 8, at least 8: every XCD queue has blocks), no more than the
-// pools need.
+// Resident blocks per CU of the persistent traversal. Every wave in flight
+// keeps its pools' part of the tree in the XCD's L2, so more waves hide more
+// latency but thin the L2 out; six blocks (24 waves) per CU gave the shortest
+// object-scale trace (58.8 ms, against 63.0 at the eight the registers allow
+// and 68.0 at four).
+constexpr int kStreamBlocksPerCu = 6;
+
+// Blocks of a persistent traversal grid: what the device holds at once, up
+// to kStreamBlocksPerCu per CU (a multiple of 8, at least 8: every XCD queue
+// has blocks), no more than the pools need.
 int64_t stream_blocks(int64_t n_pools) {
     static std::atomic<int> cached[64];
     int dev = 0;
@@ -950,7 +970,7 @@ int64_t stream_blocks(int64_t n_pools) {
             per_cu <= 0)
             per_cu = 4;
         (void)hipGetLastError();  // a failed query above must not surface as a launch error
-        nb = cus * per_cu;
+        nb = cus * std::min(per_cu, kStreamBlocksPerCu);
         if (dev >= 0 && dev < 64) cached[dev].store(nb);
     }
     int64_t want = std::min<int64_t>(nb, (n_pools + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -966,16 +986,25 @@ constexpr int64_t kListTargetWaves = 32768;
 
 void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs, int K, const Cuts &c,
                        const int64_t *ids, int64_t n_list, const unsigned long long *count, int64_t id_offset,
-                       bool out_by_value, float *out, hipStream_t stream) {
+                       bool out_by_value, float *out, unsigned long long *queues, hipStream_t stream) {
     if (n_list <= 0) return;
     const BvhLayout L = bvh_layout(g->n);
     const int64_t pools = (n_list + kPoolS * 64 - 1) / (kPoolS * 64);
+    if (queues) {
+        hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t *>(queues),
+                           (int64_t)(2 * kXcds), 0u);
+        hipLaunchKernelGGL(k_trace_list<true>, dim3((unsigned)stream_blocks(pools)), dim3(kTraceBlock), 0, stream,
+                           at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean,
+                           c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, c, ids, n_list, count,
+                           id_offset, out_by_value ? 1 : 0, (int64_t)0, queues, out);
+        return;
+    }
     const int64_t run = (pools + kListTargetWaves - 1) / kListTargetWaves;
     const int64_t waves = (pools + run - 1) / run;
-    hipLaunchKernelGGL(k_trace_list, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
+    hipLaunchKernelGGL(k_trace_list<false>, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
                        dim3(kTraceBlock), 0, stream, at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean,
                        c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, c, ids, n_list, count, id_offset,
-                       out_by_value ? 1 : 0, run, out);
+                       out_by_value ? 1 : 0, run, (unsigned long long *)nullptr, out);
 }
 
 }  // namespace rv
@@ -1055,7 +1084,8 @@ extern "C" rv_status rv_trace_rays(const void *bvh, const rv_gaussians *g, const
     RV_REQUIRE(n_rays >= 0, RV_ERR_INVALID_ARG, "rv_trace_rays: n_rays < 0");
     if (n_rays == 0) return RV_OK;
     RV_REQUIRE(ray_ids && out, RV_ERR_INVALID_ARG, "rv_trace_rays: null ray_ids or out");
-    launch_trace_list(bvh, g, dirs, K, make_cuts(*p), ray_ids, n_rays, nullptr, 0, false, out, (hipStream_t)stream);
+    launch_trace_list(bvh, g, dirs, K, make_cuts(*p), ray_ids, n_rays, nullptr, 0, false, out, nullptr,
+                      (hipStream_t)stream);
     return check_launch("rv_trace_rays");
 }
 

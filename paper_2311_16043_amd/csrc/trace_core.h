@@ -231,9 +231,11 @@ struct RingStack {
 // traversal kernels): ray j is ids[j] + id_offset = i * K + k; its T goes to
 // out[ids[j]] (out_by_value) or out[j]. With count non-null, only the first
 // min(n_list, *count) entries (read on the device) are traced. Ids outside
-// [0, n K) give NaN.
+// [0, n K) give NaN. With queues (8 counters of device scratch, cleared here)
+// a persistent grid takes the list's pools from per-XCD queues; without, each
+// wave takes a fixed run of pools.
 void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs, int K, const Cuts &c,
                        const int64_t *ids, int64_t n_list, const unsigned long long *count, int64_t id_offset,
-                       bool out_by_value, float *out, hipStream_t stream);
+                       bool out_by_value, float *out, unsigned long long *queues, hipStream_t stream);
 
 }  // namespace rv
