@@ -436,7 +436,7 @@ def main():
         "trace_ms": float(np.mean(trace_ms)),
         "trace_rays_per_s": rays / trace_s,
         "roofline": {
-            "kernel": "k_trace_pool",
+            "kernel": "k_trace_stream",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
