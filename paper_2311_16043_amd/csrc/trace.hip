@@ -47,6 +47,12 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 constexpr int kPoolS = 4;
 constexpr int kFifo = 8;
 constexpr int kPoolRing = 8;
+// The persistent all-ray and list kernels keep 16 stack entries per lane in
+// LDS (24 KB per block with the FIFO, six blocks per CU): fewer deep entries
+// go to the private spill array than with 8 (54.3 against 58.6 ms at object
+// scale). The SH and adjoint kernels, whose other LDS tables leave no room,
+// keep 8.
+constexpr int kStreamRing = 16;
 constexpr int kLeafMin = 32;
 
 struct PoolMap {
@@ -78,9 +84,9 @@ inline PoolMap make_pool(int64_t n, int K) {
 // siblings per wide level above the node, so in a tree of the bounded depth a
 // visit starts with room for its three pushes; a malformed tree (visit budget
 // spent, less room than that) ends the ray with NaN.
-template <bool kCount>
+template <bool kCount, int kRing>
 __device__ __forceinline__ void pool_node_step(const float4 *__restrict__ nodes4, f3 o, f3 inv, float tmin,
-                                               int32_t &node, int64_t &budget, RingStack<kPoolRing> &st,
+                                               int32_t &node, int64_t &budget, RingStack<kRing> &st,
                                                int32_t *my_fifo, int fhead, int &fcount, float &T, int64_t &cn) {
     if (--budget < 0) {
         node = -1;
@@ -181,8 +187,8 @@ __device__ __forceinline__ void stream_rays(const float4 *__restrict__ nodes4, c
                                             int64_t &cl, int64_t &ch) {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = (1ull << lane) - 1ull;
-    RingStack<kPoolRing> st;
-    int32_t spill[RingStack<kPoolRing>::kSpill];
+    RingStack<kStreamRing> st;
+    int32_t spill[RingStack<kStreamRing>::kSpill];
     st.lds = stk;
     st.spill = spill;
     st.stride = kTraceBlock;
@@ -389,7 +395,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__re
                                                               Cuts c, unsigned long long *__restrict__ queues,
                                                               float *__restrict__ vis_ray,
                                                               unsigned long long *__restrict__ totals) {
-    __shared__ int32_t stk[kPoolRing * kTraceBlock];
+    __shared__ int32_t stk[kStreamRing * kTraceBlock];
     __shared__ int32_t fifo[kFifo * kTraceBlock];
     const int x = (int)(blockIdx.x % kXcds);
     GridPools pools;
@@ -433,7 +439,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_list(
     int K, Cuts c, const int64_t *__restrict__ ids, int64_t n_list, const unsigned long long *__restrict__ count,
     int64_t id_offset, int out_by_value, int64_t run, unsigned long long *__restrict__ queues,
     float *__restrict__ out) {
-    __shared__ int32_t stk[kPoolRing * kTraceBlock];
+    __shared__ int32_t stk[kStreamRing * kTraceBlock];
     __shared__ int32_t fifo[kFifo * kTraceBlock];
     constexpr int kPool = kPoolS * 64;
     const int64_t total = count ? min<int64_t>(n_list, (int64_t)*count) : n_list;
