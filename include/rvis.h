@@ -229,6 +229,10 @@ rv_status rv_trace_visibility_sh(const void *bvh, const rv_gaussians *g, const f
  * totals[0] = four-wide node visits, totals[1] = leaf records tested,
  * totals[2] = Gaussians included, summed over all n*K rays (int64, overwritten).
  * Used to compute algorithmic bytes; runs a separate instrumented kernel.
+ * totals[1] and totals[2] are fixed by the rays; totals[0] can vary by a few
+ * visits between runs: a ray keeps walking while the leaves it found wait for
+ * its wave's leaf test, and the visits made before the leaf that ends it by
+ * T < T_min depend on scheduling (its T does not).
  * ws: at least 256 bytes of device scratch, 256-byte aligned (work-queue
  * counters). Errors: as rv_trace_visibility.
  */

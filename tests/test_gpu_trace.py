@@ -168,7 +168,10 @@ def test_stats_are_consistent():
     bvh = build_bvh(g)
     st = trace_stats(bvh, g, dirs)
     st2 = trace_stats(bvh, g, dirs)
-    assert st == st2
+    # leaf tests and inclusions are fixed by the rays; node visits made while a
+    # ray's last leaves wait for the wave's leaf phase depend on scheduling
+    assert st["leaves"] == st2["leaves"] and st["hits"] == st2["hits"]
+    assert abs(st["nodes"] - st2["nodes"]) <= 1e-4 * st["nodes"]
     rays = 20_000 * 32
     assert st["nodes"] >= rays and st["leaves"] >= st["hits"] > 0
     # brute force tests n-1 Gaussians per ray; the BVH must test far fewer
