@@ -288,6 +288,10 @@ struct GridSource {
     float tmin_scale;
     float inv_nv;  // reciprocal of nv (within one ulp)
     int K = 0;
+    // output position: i * K + k (by_leaf false), or (m - m_lo) * K + k with m
+    // the Gaussian's sorted position (by_leaf true: rows of a batch)
+    bool by_leaf = false;
+    int64_t m_lo = 0;
     __device__ __forceinline__ RaySetup operator()(int idx) const {
         // idx / nv from the float quotient: (idx + 1/2) / nv lies at least
         // 1/(2 nv) >= 1/128 from an integer, far beyond its rounding error
@@ -307,22 +311,23 @@ struct GridSource {
         r.self = __float_as_int(rec[kLeafF4 * m + 2].w);
         r.self_leaf = (int32_t)m;
         r.valid = true;
-        r.out = (int64_t)r.self * K + k0 + j;
+        r.out = (by_leaf ? m - m_lo : (int64_t)r.self) * K + k0 + j;
         return r;
     }
 };
 
 // All-ray pools: pool p = group * n_chunks + chunk covers the 64 Gaussians
-// of the group (sorted order) times the chunk's kStreamPoolS directions.
+// of the group (sorted order, groups counted from m_lo) times the chunk's
+// kStreamPoolS directions.
 struct GridPools : GridSource {
-    int64_t n;
+    int64_t m_hi;  // the pools cover sorted positions [m_lo, m_hi)
     int n_chunks;
     // Make pool p current; returns its number of rays.
     __device__ __forceinline__ int open(int64_t p) {
         const int64_t grp = p / n_chunks;
         const int chunk = (int)(p - grp * n_chunks);
-        m0 = grp * 64;
-        nv = (int)min<int64_t>(64, n - m0);
+        m0 = m_lo + grp * 64;
+        nv = (int)min<int64_t>(64, m_hi - m0);
         inv_nv = __builtin_amdgcn_rcpf((float)nv);
         k0 = chunk * kStreamPoolS;
         return nv * min(kStreamPoolS, K - k0);
@@ -388,7 +393,8 @@ struct ListPools : ListSource {
     }
 };
 
-// All n K rays through per-XCD queues of pools. The grid is persistent (a
+// The rays of the Gaussians at sorted positions [m_lo, m_hi) (all n K rays
+// for [0, n)) through per-XCD queues of pools. The grid is persistent (a
 // multiple of 8 blocks, about what the device holds at once) and block b
 // serves the queue of XCD b % 8 (round-robin dispatch), whose range is a
 // contiguous eighth of the pools: each L2 sees a compact part of the tree.
@@ -397,7 +403,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__re
                                                               const float4 *__restrict__ rec,
                                                               const float4 *__restrict__ origins,
                                                               const float *__restrict__ dirs, int64_t n, int K,
-                                                              Cuts c, unsigned long long *__restrict__ queues,
+                                                              Cuts c, int64_t m_lo, int64_t m_hi, int by_leaf,
+                                                              unsigned long long *__restrict__ queues,
                                                               float *__restrict__ vis_ray,
                                                               unsigned long long *__restrict__ totals) {
     __shared__ int32_t stk[kStreamRing * kTraceBlock];
@@ -410,13 +417,15 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__re
     pools.dir_mode = c.dir_mode;
     pools.tmin_scale = c.tmin_scale;
     pools.K = K;
-    pools.n = n;
+    pools.by_leaf = by_leaf != 0;
+    pools.m_lo = m_lo;
+    pools.m_hi = m_hi;
     pools.n_chunks = (K + kStreamPoolS - 1) / kStreamPoolS;
     pools.m0 = 0;
     pools.nv = 1;
     pools.k0 = 0;
     pools.inv_nv = 1.0f;
-    const int64_t n_pools = ((n + 63) / 64) * (int64_t)pools.n_chunks;
+    const int64_t n_pools = ((m_hi - m_lo + 63) / 64) * (int64_t)pools.n_chunks;
     XcdQueue q;
     q.ctr = queues + x;
     q.begin = n_pools * x / kXcds;
@@ -502,35 +511,19 @@ __global__ __launch_bounds__(256) void k_mean_rows(const float *__restrict__ vis
 // spherical harmonics of degree <= 2 (9 coefficients, the "3-level SH" of
 // Sec. 3.3) by the quadrature of Eq. (10): v_ij = sum_k V_ik Y_j(d_k) dw, with
 // d_k the table's unit directions in the rays' frame (local about the normal
-// in hemisphere mode). No per-ray output: a wave takes 64 adjacent Gaussians
-// through a run of direction chunks, draining each chunk's pool as the
-// all-ray kernel does, and each lane adds its Gaussian's rays in a fixed order.
-// A few runs per Gaussian group keep enough waves in flight; their FP64
-// partials are added in run order (deterministic).
+// in hemisphere mode). No per-ray output reaches the caller: the Gaussians are
+// traced in batches of consecutive sorted positions by the persistent all-ray
+// kernel into a bounded buffer of rows, and each row is projected in FP64 in a
+// fixed order (deterministic).
 constexpr int kShCoef = 9;
-constexpr int kShSums = kShCoef + 1;   // the 9 projections and the plain sum of V
-constexpr int64_t kShTargetWaves = 65536;
+// Per-ray values held per batch: at most 2^26 (256 MB).
+constexpr int64_t kShBatchRays = int64_t(1) << 26;
 
-struct ShMap {
-    int64_t n;
-    int K, n_chunks, n_runs, chunks_per_run;
-    int64_t n_items;   // ceil(n / 64) * n_runs
-    int64_t w_off;
-};
-
-inline ShMap make_sh_map(int64_t n, int K) {
-    ShMap m;
-    m.n = n;
-    m.K = K;
-    m.n_chunks = (K + kPoolS - 1) / kPoolS;
-    const int64_t groups = (n + 63) / 64;
-    int64_t runs = (kShTargetWaves + groups - 1) / groups;
-    runs = std::max<int64_t>(1, std::min<int64_t>(runs, m.n_chunks));
-    m.chunks_per_run = (int)((m.n_chunks + runs - 1) / runs);
-    m.n_runs = (m.n_chunks + m.chunks_per_run - 1) / m.chunks_per_run;
-    m.n_items = groups * (int64_t)m.n_runs;
-    m.w_off = 0;
-    return m;
+// Gaussians per batch: a multiple of 64, at least 64, at most n.
+inline int64_t sh_batch(int64_t n, int K) {
+    int64_t b = kShBatchRays / K / 64 * 64;
+    b = std::max<int64_t>(b, 64);
+    return std::min<int64_t>(b, n);
 }
 
 // Real SH of degree <= 2 at the unit direction of table entry k.
@@ -549,160 +542,47 @@ __device__ __forceinline__ void sh_of_dir(const float *__restrict__ dirs, int k,
     Y[8] = 0.5462742152960396f * (x * x - y * y);
 }
 
-constexpr int kShRing = 8;   // direction rows held in the result ring
-
-__global__ __launch_bounds__(kTraceBlock) void k_trace_sh(const float4 *__restrict__ nodes4,
-                                                          const float4 *__restrict__ rec,
-                                                          const float4 *__restrict__ origins,
-                                                          const float *__restrict__ dirs, ShMap sm, Cuts c,
-                                                          double *__restrict__ partial) {
-    __shared__ int32_t stk[kPoolRing * kTraceBlock];
-    __shared__ int32_t fifo[kFifo * kTraceBlock];
-    __shared__ float ring[kWavesPerBlock][kShRing * 64];
-    __shared__ int32_t done_cnt[kWavesPerBlock][kShRing];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t w = sm.w_off + xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
-    if (w >= sm.n_items) return;  // wave-uniform
-    const int64_t grp = w / sm.n_runs;
-    const int run = (int)(w - grp * sm.n_runs);
-    GridSource src;
-    src.rec = rec;
-    src.origins = origins;
-    src.dirs = dirs;
-    src.m0 = grp * 64;
-    src.nv = (int)min<int64_t>(64, sm.n - src.m0);
-    src.inv_nv = __builtin_amdgcn_rcpf((float)src.nv);
-    src.k0 = run * sm.chunks_per_run * kPoolS;
-    src.dir_mode = c.dir_mode;
-    src.tmin_scale = c.tmin_scale;
-    const int nv = src.nv;
-    // the run's directions k0 .. k0 + rows - 1, one row of nv rays each;
-    // pool index idx = row * nv + origin
-    const int rows = min(sm.chunks_per_run * kPoolS, sm.K - src.k0);
-    const int pool_n = rows * nv;
-    if (lane < kShRing) done_cnt[wv][lane] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-
-    float acc[kShSums];
+// Y[k][j] = Y_j(d_k) for the K table directions.
+__global__ __launch_bounds__(256) void k_sh_table(const float *__restrict__ dirs, int K, float *__restrict__ Y) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    float y[kShCoef];
+    sh_of_dir(dirs, k, y);
 #pragma unroll
-    for (int q = 0; q < kShSums; ++q) acc[q] = 0.0f;
-    const uint64_t lt = (1ull << lane) - 1ull;
-    RingStack<kPoolRing> st;
-    int32_t spill[RingStack<kPoolRing>::kSpill];
-    st.lds = stk + threadIdx.x;
-    st.spill = spill;
-    st.stride = kTraceBlock;
-    st.sp = 0;
-    int32_t *my_fifo = fifo + threadIdx.x;
-    int fhead = 0, fcount = 0;
-    bool has = false;
-    int row = 0, oi = 0;  // direction row and origin of the current ray
-    f3 o = mk(0.f, 0.f, 0.f), d = o, inv = o;
-    float tmin = 0.f, T = 1.f;
-    int32_t self = -1, self_leaf = -1, node = -1;
-    int64_t budget = 0, cn = 0;
-    NoHit none;
-    int next = 0;      // next pool index to hand out (wave-uniform)
-    int consumed = 0;  // rows already added to the sums (wave-uniform)
-
-    while (consumed < rows) {
-        // refill idle lanes, never more than kShRing rows ahead of the sums
-        const int avail = min(pool_n, (consumed + kShRing) * nv);
-        const uint64_t need = __ballot(!has);
-        if (need != 0 && next < avail) {
-            const int idx = next + __popcll(need & lt);
-            if (!has && idx < avail) {
-                const RaySetup r = src(idx);
-                o = r.o;
-                d = r.d;
-                inv = safe_inv(d);
-                tmin = r.tmin;
-                self = r.self;
-                self_leaf = r.self_leaf;
-                T = 1.0f;
-                st.sp = 0;
-                fhead = 0;
-                fcount = 0;
-                node = sm.n > 1 ? 0 : -1;
-                budget = sm.n;
-                row = idx / nv;
-                oi = idx - row * nv;
-                has = true;
-            }
-            next = min(avail, next + __popcll(need));
-        }
-
-        if (has && node >= 0 && fcount <= kFifo - 4)
-            pool_node_step<false>(nodes4, o, inv, tmin, node, budget, st, my_fifo, fhead, fcount, T, cn);
-
-        if (leaf_phase_now(has, node, fcount)) {
-            if (has && fcount > 0) {
-                const int32_t leaf = my_fifo[fhead * kTraceBlock];
-                fhead = (fhead + 1) & (kFifo - 1);
-                --fcount;
-                T *= leaf_factor(rec, leaf, o, d, tmin, self, self_leaf, c, none, T);
-                if (T < c.T_stop) {
-                    node = -1;
-                    fcount = 0;
-                }
-            }
-        }
-
-        // finished rays park T in their row's ring slot and count the row
-        const bool finished = has && node < 0 && fcount == 0;
-        if (finished) {
-            const int slot = row & (kShRing - 1);
-            ring[wv][slot * 64 + oi] = T;
-            atomicAdd(&done_cnt[wv][slot], 1);
-            has = false;
-        }
-        if (__ballot(finished) == 0) continue;  // no row can have completed
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        // add completed rows to the sums strictly in row order (deterministic);
-        // every lane reads the same counter, so the loop is wave-uniform
-        while (consumed < rows && done_cnt[wv][consumed & (kShRing - 1)] == nv) {
-            const int slot = consumed & (kShRing - 1);
-            if (lane < nv) {
-                const float t = ring[wv][slot * 64 + lane];
-                float Y[kShCoef];
-                sh_of_dir(dirs, src.k0 + consumed, Y);
-#pragma unroll
-                for (int q = 0; q < kShCoef; ++q) acc[q] = fmaf(t, Y[q], acc[q]);
-                acc[kShCoef] += t;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) done_cnt[wv][slot] = 0;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            ++consumed;
-        }
-    }
-    if (lane < nv) {
-        const int64_t me = __float_as_int(rec[kLeafF4 * (src.m0 + lane) + 2].w);
-#pragma unroll
-        for (int q = 0; q < kShSums; ++q) partial[((int64_t)run * kShSums + q) * sm.n + me] = (double)acc[q];
-    }
+    for (int j = 0; j < kShCoef; ++j) Y[k * kShCoef + j] = y[j];
 }
 
-// vis_sh[i][j] = dw * (sum over runs, in run order, of the partials);
-// vis_mean[i] = (sum of V over runs) / K.
-__global__ __launch_bounds__(256) void k_sh_from_partials(const double *__restrict__ partial, int64_t n, int n_runs,
-                                                          int K, double dw, float *__restrict__ vis_sh,
-                                                          float *__restrict__ vis_mean) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s[kShSums];
+// Rows m_lo .. m_lo + n_rows - 1 (sorted positions) of a traced batch: one
+// wave per row adds T_k Y_j(d_k) and T_k over k in FP64, lanes over a fixed
+// stride and a fixed butterfly; vis_sh and vis_mean go to the Gaussian's
+// original index.
+__global__ __launch_bounds__(256) void k_sh_rows(const float *__restrict__ rows, int64_t m_lo, int64_t n_rows, int K,
+                                                 const float *__restrict__ Y, const float4 *__restrict__ rec,
+                                                 double dw, float *__restrict__ vis_sh,
+                                                 float *__restrict__ vis_mean) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n_rows; r += (int64_t)gridDim.x * 4) {
+        const float *row = rows + r * K;
+        double acc[kShCoef + 1];
 #pragma unroll
-    for (int q = 0; q < kShSums; ++q) s[q] = 0.0;
-    for (int r = 0; r < n_runs; ++r)
+        for (int j = 0; j <= kShCoef; ++j) acc[j] = 0.0;
+        for (int k = lane; k < K; k += 64) {
+            const double t = (double)row[k];
 #pragma unroll
-        for (int q = 0; q < kShSums; ++q) s[q] += partial[((int64_t)r * kShSums + q) * n + i];
+            for (int j = 0; j < kShCoef; ++j) acc[j] += t * (double)Y[k * kShCoef + j];
+            acc[kShCoef] += t;
+        }
 #pragma unroll
-    for (int q = 0; q < kShCoef; ++q) vis_sh[i * kShCoef + q] = (float)(s[q] * dw);
-    if (vis_mean) vis_mean[i] = (float)(s[kShCoef] / (double)K);
+        for (int j = 0; j <= kShCoef; ++j)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
+        if (lane == 0) {
+            const int64_t i = __float_as_int(rec[kLeafF4 * (m_lo + r) + 2].w);
+#pragma unroll
+            for (int j = 0; j < kShCoef; ++j) vis_sh[i * kShCoef + j] = (float)(acc[j] * dw);
+            if (vis_mean) vis_mean[i] = (float)(acc[kShCoef] / (double)K);
+        }
+    }
 }
 
 // ---- adjoint ----------------------------------------------------------------
@@ -1034,15 +914,17 @@ namespace {
 // when counting).
 template <bool kCount>
 void launch_trace_stream(const void *bvh, const rv_gaussians *g, const float *dirs, int K, const Cuts &c,
-                         void *ws, float *vis_ray, unsigned long long *totals, hipStream_t s) {
+                         void *ws, float *vis_ray, unsigned long long *totals, hipStream_t s, int64_t m_lo = 0,
+                         int64_t m_hi = -1, bool by_leaf = false) {
     const BvhLayout L = bvh_layout(g->n);
-    const int64_t n_pools = ((g->n + 63) / 64) * (int64_t)((K + kStreamPoolS - 1) / kStreamPoolS);
+    if (m_hi < 0) m_hi = g->n;
+    const int64_t n_pools = ((m_hi - m_lo + 63) / 64) * (int64_t)((K + kStreamPoolS - 1) / kStreamPoolS);
     auto *queues = static_cast<unsigned long long *>(ws);
     hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(queues),
                        (int64_t)(2 * kXcds), 0u);
     hipLaunchKernelGGL(k_trace_stream<kCount>, dim3((unsigned)stream_blocks(n_pools)), dim3(kTraceBlock), 0, s,
                        at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, g->n,
-                       K, c, queues, vis_ray, totals);
+                       K, c, m_lo, m_hi, by_leaf ? 1 : 0, queues, vis_ray, totals);
 }
 
 }  // namespace
@@ -1128,8 +1010,8 @@ extern "C" rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaus
 
 extern "C" size_t rv_trace_sh_workspace_bytes(int64_t n, int32_t K) {
     if (n < 1 || K < 1) return 0;
-    const ShMap sm = make_sh_map(n, K);
-    return align_up((size_t)sm.n_runs * kShSums * (size_t)n * sizeof(double));
+    return kAlign + align_up((size_t)K * kShCoef * sizeof(float)) +
+           align_up((size_t)sh_batch(n, K) * (size_t)K * sizeof(float));
 }
 
 extern "C" rv_status rv_trace_visibility_sh(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
@@ -1143,20 +1025,22 @@ extern "C" rv_status rv_trace_visibility_sh(const void *bvh, const rv_gaussians 
     RV_REQUIRE(ws && ((uintptr_t)ws % kAlign) == 0, RV_ERR_INVALID_ARG,
                "rv_trace_visibility_sh: ws missing or unaligned");
     RV_REQUIRE(ws_bytes >= need, RV_ERR_WORKSPACE, "rv_trace_visibility_sh: ws_bytes %zu < %zu", ws_bytes, need);
-    const ShMap sm = make_sh_map(g->n, K);
+    // ws: queue counters | Y table [K][9] | rows of one batch [batch][K]
+    float *Y = reinterpret_cast<float *>(static_cast<char *>(ws) + kAlign);
+    float *rows = reinterpret_cast<float *>(static_cast<char *>(ws) + kAlign +
+                                            align_up((size_t)K * kShCoef * sizeof(float)));
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
     hipStream_t s = (hipStream_t)stream;
-    double *partial = static_cast<double *>(ws);
-    for (int64_t w0 = 0; w0 < sm.n_items; w0 += kLaunchWaves) {
-        ShMap part = sm;
-        part.w_off = w0;
-        const int64_t nb = (std::min(kLaunchWaves, sm.n_items - w0) + kWavesPerBlock - 1) / kWavesPerBlock;
-        hipLaunchKernelGGL(k_trace_sh, dim3((unsigned)nb), dim3(kTraceBlock), 0, s, at<float4>(bvh, L.nodes4),
-                           at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, part, c, partial);
-    }
+    hipLaunchKernelGGL(k_sh_table, dim3(grid_for(K, 256)), dim3(256), 0, s, dirs, (int)K, Y);
     const double dw = (p->dir_mode ? 2.0 : 4.0) * 3.14159265358979323846 / (double)K;
-    hipLaunchKernelGGL(k_sh_from_partials, dim3(grid_for(g->n, 256)), dim3(256), 0, s, partial, g->n, sm.n_runs, K,
-                       dw, vis_sh, vis_mean);
+    const int64_t batch = sh_batch(g->n, K);
+    for (int64_t m_lo = 0; m_lo < g->n; m_lo += batch) {
+        const int64_t m_hi = std::min(g->n, m_lo + batch);
+        launch_trace_stream<false>(bvh, g, dirs, K, c, ws, rows, nullptr, s, m_lo, m_hi, true);
+        const int64_t blocks = std::min<int64_t>((m_hi - m_lo + 3) / 4, int64_t(1) << 20);
+        hipLaunchKernelGGL(k_sh_rows, dim3((unsigned)blocks), dim3(256), 0, s, rows, m_lo, m_hi - m_lo, (int)K, Y,
+                           at<float4>(bvh, L.leaf_rec), dw, vis_sh, vis_mean);
+    }
     return check_launch("rv_trace_visibility_sh");
 }

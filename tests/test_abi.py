@@ -151,10 +151,13 @@ def test_sh_workspace_and_rejects_bad_arguments(lib):
     assert lib.rv_trace_sh_workspace_bytes(0, 8) == 0
     assert lib.rv_trace_sh_workspace_bytes(10, 0) == 0
     prev = 0
-    for n, K in ((1, 1), (10, 8), (1000, 256), (300_000, 256)):
+    for n, K in ((1, 1), (10, 8), (1000, 256), (300_000, 256), (3_000_000, 1024)):
         b = lib.rv_trace_sh_workspace_bytes(n, K)
-        # at least one run of 10 FP64 sums per Gaussian, 256-byte aligned
-        assert b % 256 == 0 and b >= n * 10 * 8 and b >= prev
+        # queue counters, the K x 9 table and one batch of per-ray values
+        # (all n rows up to 2^26 values, never more than 2^26 + a table)
+        rows = min(n * K, 1 << 26)
+        assert b % 256 == 0 and b >= 256 + K * 9 * 4 + rows * 4 and b >= prev
+        assert b <= 256 + K * 9 * 4 + (1 << 26) * 4 + 1024
         prev = b
     P = 1 << 40
     g = _g()
