@@ -120,6 +120,21 @@ def test_ray_list_matches_full_trace_bitwise():
     assert np.array_equal(got.view(np.uint32), vr.reshape(-1)[ids].view(np.uint32))
 
 
+def test_long_ray_list_in_runs_matches_full_trace_bitwise():
+    """9M listed rays: past 32,768 pools of 256, so each wave of the list kernel
+    takes a run of two pools; every ray must still equal the all-ray trace."""
+    sc = scenes.make_scene("object")
+    dirs = scenes.preset_dirs("object")
+    n, K = sc["mean"].shape[0], dirs.shape[0]
+    g, bvh, vr, _ = _run(sc, dirs, TraceParams())
+    ids = np.sort(np.random.default_rng(21).choice(n * K, 9_000_000, replace=False)).astype(np.int64)
+    got = trace_rays(bvh, g, dirs, ids, TraceParams()).cpu().numpy()
+    want = vr.reshape(-1)[ids]
+    bad = int(np.count_nonzero(got.view(np.uint32) != want.view(np.uint32)))
+    print(f"[long list] {ids.size} rays, mismatches {bad}", flush=True)
+    assert bad == 0
+
+
 def test_trace_is_deterministic():
     sc = scenes.make_object_scene(30_000, 1)
     dirs = scenes.fibonacci_dirs(64, True)
