@@ -344,7 +344,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the path shards by origin ranges, see DESIGN.md)", file=sys.stderr)
+              f"(the path would shard by contiguous Morton ranges of origins, one range per GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2311_16043_amd import Gaussians, TraceParams, build_bvh, trace_stats, trace_visibility
