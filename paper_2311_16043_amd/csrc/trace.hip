@@ -91,7 +91,7 @@ inline PoolMap make_pool(int64_t n, int K) {
 // spent, less room than that) ends the ray with NaN.
 template <bool kCount, int kRing>
 __device__ __forceinline__ void pool_node_step(const float4 *__restrict__ nodes4, f3 o, f3 inv, float tmin,
-                                               int32_t &node, int64_t &budget, RingStack<kRing> &st,
+                                               int32_t &node, int32_t &budget, RingStack<kRing> &st,
                                                int32_t *my_fifo, int fhead, int &fcount, float &T, int64_t &cn) {
     if (--budget < 0) {
         node = -1;
@@ -160,10 +160,12 @@ struct RaySetup {
 struct XcdQueue {
     unsigned long long *ctr;
     int64_t begin, end;
-    // Next pool in p, false once the range is spent. Called by all lanes.
+    // Next pool in p, false once the range is spent. Called in wave-uniform
+    // control flow; the first active lane takes the pool for the wave.
     __device__ __forceinline__ bool take(int64_t &p) {
+        const int lane = threadIdx.x & 63;
         unsigned long long t = 0;
-        if ((threadIdx.x & 63) == 0) t = atomicAdd(ctr, 1ull);
+        if (lane == __builtin_amdgcn_readfirstlane(lane)) t = atomicAdd(ctr, 1ull);
         const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t);
         const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(t >> 32));
         p = begin + (int64_t)(((uint64_t)hi << 32) | lo);
@@ -204,7 +206,7 @@ __device__ __forceinline__ void stream_rays(const float4 *__restrict__ nodes4, c
     f3 o = mk(0.f, 0.f, 0.f), d = o, inv = o;
     float tmin = 0.f, T = 1.f;
     int32_t self = -1, self_leaf = -1, node = -1;
-    int64_t budget = 0;
+    int32_t budget = 0;  // node visits left (n <= 2^30)
     NoHit none;
     // wave-uniform pool state
     int next = 0, pool_n = 0;
@@ -235,7 +237,7 @@ __device__ __forceinline__ void stream_rays(const float4 *__restrict__ nodes4, c
                 fhead = 0;
                 fcount = 0;
                 node = r.valid && n > 1 ? 0 : -1;
-                budget = n;
+                budget = (int32_t)n;
                 dst = r.out;
                 has = true;
             }
@@ -704,7 +706,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     f3 o = mk(0.f, 0.f, 0.f), d = o, inv = o;
     float tmin = 0.f, T = 1.f;
     int32_t self = -1, self_leaf = -1, node = -1;
-    int64_t budget = 0;
+    int32_t budget = 0;
     int64_t cn = 0;
     GradScatter gs;
     gs.active = false;
@@ -721,7 +723,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
         fhead = 0;
         fcount = 0;
         node = pm.n > 1 ? 0 : -1;
-        budget = pm.n;
+        budget = (int32_t)pm.n;
     };
 
     while (true) {
