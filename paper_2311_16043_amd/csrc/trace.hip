@@ -5,13 +5,15 @@
 //
 // Work mapping. Rays come in pools (see the pooled traversal below): 64
 // Gaussians adjacent in Morton (sorted-leaf) order times one direction for the
-// persistent all-ray kernel, times a chunk of 4 consecutive directions for the
-// SH and adjoint kernels, 256 consecutive entries for the list kernel. The all-ray forward runs a persistent grid that takes pools
-// from eight queues, one per XCD, each a contiguous eighth of the Morton
-// order, so each L2 sees a compact part of the tree; a wave keeps its lanes
-// supplied across pool boundaries, so the skewed per-ray work leaves lanes
-// idle only in a wave's last pool. Each ray writes its own T; per-Gaussian
-// means are FP64 row sums in a fixed order (deterministic, no atomics).
+// persistent all-ray kernel (which also serves the SH projection), times a
+// chunk of 4 consecutive directions for the adjoint kernel, and 256
+// consecutive entries for the list kernel. The all-ray forward runs a
+// persistent grid that takes pools from eight queues, one per XCD, each a
+// contiguous eighth of the Morton order, so each L2 sees a compact part of the
+// tree; a wave keeps its lanes supplied across pool boundaries, so the skewed
+// per-ray work leaves lanes idle only in a wave's last pool. Each ray writes
+// its own T; per-Gaussian means are FP64 row sums in a fixed order
+// (deterministic, no atomics).
 #include <atomic>
 #include <type_traits>
 
@@ -34,24 +36,23 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 
 // ---- pooled traversal -----------------------------------------------------------
 //
-// A wave owns a pool of rays: 64 Gaussians adjacent in sorted order times a
-// chunk of kPoolS consecutive directions. Lanes that have no ray take the next
-// pool rays (ballot + popcount). Each iteration, lanes with traversal work and
-// room in their leaf FIFO visit one node, appending hit leaves instead of
-// testing them; the leaf test then runs as one block for all lanes with a
-// pending leaf once enough of them have one, so the expensive exact test
-// executes with most lanes active instead of inside every node step. Leaves
-// are tested in discovery (FIFO) order, so each ray's product, and its early
-// exit, do not depend on which pool the ray was drained from: the all-ray,
-// ray-list and adjoint kernels give a ray the same bits.
+// A wave drains pools of rays (64 Gaussians adjacent in sorted order times
+// some directions, or consecutive list entries). Lanes that have no ray take
+// the pool's next rays (ballot + popcount). Each iteration, lanes with
+// traversal work and room in their leaf FIFO visit one node, appending hit
+// leaves instead of testing them; the leaf test then runs as one block for
+// all lanes with a pending leaf once enough of them have one, so the
+// expensive exact test executes with most lanes active instead of inside
+// every node step. Leaves are tested in discovery (FIFO) order, so each ray's
+// product, and its early exit, do not depend on which pool the ray was drained
+// from: the all-ray, ray-list, SH and adjoint paths give a ray the same bits.
 constexpr int kPoolS = 4;
 constexpr int kFifo = 8;
 constexpr int kPoolRing = 8;
 // The persistent all-ray and list kernels keep 16 stack entries per lane in
 // LDS (24 KB per block with the FIFO, six blocks per CU): fewer deep entries
 // go to the private spill array than with 8 (54.3 against 58.6 ms at object
-// scale). The SH and adjoint kernels, whose other LDS tables leave no room,
-// keep 8.
+// scale). The adjoint kernel, whose gradient table leaves no room, keeps 8.
 constexpr int kStreamRing = 16;
 // Directions per pool of the persistent all-ray kernel. With one, the pools
 // in flight on an XCD cover the fewest Gaussians (about 256 against 1,024
