@@ -659,38 +659,48 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     const float *__restrict__ grad_mean_in, const float *__restrict__ vis_fwd, float *go, float *gm, float *gl) {
     __shared__ int32_t stk[kPoolRing * kTraceBlock];
     __shared__ int32_t fifo[kFifo * kTraceBlock];
-    __shared__ float ogr[kWavesPerBlock][64 * 3];
+    __shared__ float ogr[kWavesPerBlock][64 * 3];   // origin terms per item
     __shared__ GradTable table;
+    // the block's four items (64 Gaussians x a chunk of directions each),
+    // drained together: item sizes, their Gaussians and first directions
+    __shared__ int item_n[kWavesPerBlock], item_nv[kWavesPerBlock], item_k0[kWavesPerBlock];
+    __shared__ int64_t item_m0[kWavesPerBlock];
+    __shared__ int blk_next;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int s = threadIdx.x; s < kHashSlots; s += kTraceBlock) {
         table.key[s] = -1;
 #pragma unroll
         for (int c = 0; c < 7; ++c) table.val[c][s] = 0.0f;
     }
-    __syncthreads();
-    // every wave reaches the final barrier; waves past the end trace nothing
+    // item wv: every wave reaches the barriers; items past the end are empty
     int64_t w = pm.w_off + xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
     const bool wave_live = w < pm.n_items;
     if (!wave_live) w = 0;
     const int64_t grp = w / pm.n_chunks;
     const int chunk = (int)(w - grp * pm.n_chunks);
+    const int64_t my_m0 = grp * 64;
+    const int my_nv = (int)min<int64_t>(64, pm.n - my_m0);
+    const int K = pm.K;
+    if (lane == 0) {
+        item_n[wv] = wave_live ? my_nv * min(kPoolS, K - chunk * kPoolS) : 0;
+        item_nv[wv] = my_nv;
+        item_k0[wv] = chunk * kPoolS;
+        item_m0[wv] = my_m0;
+    }
+    if (threadIdx.x == 0) blk_next = 0;
+    ogr[wv][lane] = 0.f;
+    ogr[wv][64 + lane] = 0.f;
+    ogr[wv][128 + lane] = 0.f;
+    __syncthreads();
+    // block ray r: item it with n_0 + .. + n_(it-1) <= r, local index r - that sum
+    const int n_a = item_n[0], n_b = n_a + item_n[1], n_c = n_b + item_n[2], total = n_c + item_n[3];
     GridSource src;
     src.rec = rec;
     src.origins = origins;
     src.dirs = dirs;
-    src.m0 = grp * 64;
-    src.nv = (int)min<int64_t>(64, pm.n - src.m0);
-    src.inv_nv = __builtin_amdgcn_rcpf((float)src.nv);
-    src.k0 = chunk * kPoolS;
     src.dir_mode = c.dir_mode;
     src.tmin_scale = c.tmin_scale;
-    const int pool_n = wave_live ? src.nv * min(kPoolS, pm.K - src.k0) : 0;
-    const int K = pm.K;
-    ogr[wv][lane] = 0.f;
-    ogr[wv][64 + lane] = 0.f;
-    ogr[wv][128 + lane] = 0.f;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
+    src.K = K;
 
     const uint64_t lt = (1ull << lane) - 1ull;
     RingStack<kPoolRing> st;
@@ -702,8 +712,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     int32_t *my_fifo = fifo + threadIdx.x;
     int fhead = 0, fcount = 0;
     bool has = false;
-    int oi = 0;        // pool origin of the current ray
-    float gk = 0.f;    // upstream gradient of the current ray
+    int oi = 0, it = 0;  // item and item origin of the current ray
+    float gk = 0.f;      // upstream gradient of the current ray
     f3 o = mk(0.f, 0.f, 0.f), d = o, inv = o;
     float tmin = 0.f, T = 1.f;
     int32_t self = -1, self_leaf = -1, node = -1;
@@ -717,7 +727,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     gs.gl = gl;
     gs.table = &table;
     gs.origin = mk(0.f, 0.f, 0.f);
-    int next = 0;  // wave-uniform
+    bool drained = false;  // wave-uniform: the block's rays are all handed out
     auto restart = [&]() {
         T = 1.0f;
         st.sp = 0;
@@ -729,14 +739,25 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
 
     while (true) {
         const uint64_t need = __ballot(!has);
-        if (need != 0 && next < pool_n) {
-            const int idx = next + __popcll(need & lt);
-            if (!has && idx < pool_n) {
-                const RaySetup r = src(idx);
-                oi = idx % src.nv;
-                const int k = src.k0 + idx / src.nv;
-                gk = (grad_mean_in ? grad_mean_in[r.self] / (float)K : 0.0f) +
-                     (grad_ray ? grad_ray[(int64_t)r.self * K + k] : 0.0f);
+        if (need != 0 && !drained) {
+            // the wave's first active lane reserves one block ray per idle lane
+            const int cnt = __popcll(need);
+            int base = 0;
+            if (lane == __builtin_amdgcn_readfirstlane(lane)) base = atomicAdd(&blk_next, cnt);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if (base + cnt >= total) drained = true;
+            const int idx = base + __popcll(need & lt);
+            if (!has && idx < total) {
+                it = (idx >= n_a) + (idx >= n_b) + (idx >= n_c);
+                const int local = idx - (it == 0 ? 0 : it == 1 ? n_a : it == 2 ? n_b : n_c);
+                src.m0 = item_m0[it];
+                src.nv = item_nv[it];
+                src.inv_nv = __builtin_amdgcn_rcpf((float)src.nv);
+                src.k0 = item_k0[it];
+                const RaySetup r = src(local);
+                oi = (int)(r.self_leaf - src.m0);
+                // r.out = i K + k: the ray's place in grad_ray and vis_fwd
+                gk = (grad_mean_in ? grad_mean_in[r.self] / (float)K : 0.0f) + (grad_ray ? grad_ray[r.out] : 0.0f);
                 o = r.o;
                 d = r.d;
                 inv = safe_inv(d);
@@ -746,14 +767,13 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
                 restart();
                 gs.origin = mk(0.f, 0.f, 0.f);
                 gs.active = vis_fwd != nullptr;
-                gs.g_over = vis_fwd ? -gk * vis_fwd[(int64_t)r.self * K + k] : 0.0f;
+                gs.g_over = vis_fwd ? -gk * vis_fwd[r.out] : 0.0f;
                 if (gk == 0.0f) {   // nothing to propagate: the ray ends here
                     node = -1;
                     gs.active = true;
                 }
                 has = true;
             }
-            next += __popcll(need);
         }
         if (__ballot(has) == 0) break;
 
@@ -781,27 +801,27 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
                 restart();
             } else {
                 if (gs.origin.x != 0.f || gs.origin.y != 0.f || gs.origin.z != 0.f) {
-                    atomicAdd(&ogr[wv][3 * oi + 0], gs.origin.x);
-                    atomicAdd(&ogr[wv][3 * oi + 1], gs.origin.y);
-                    atomicAdd(&ogr[wv][3 * oi + 2], gs.origin.z);
+                    atomicAdd(&ogr[it][3 * oi + 0], gs.origin.x);
+                    atomicAdd(&ogr[it][3 * oi + 1], gs.origin.y);
+                    atomicAdd(&ogr[it][3 * oi + 2], gs.origin.z);
                 }
                 has = false;
             }
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    if (wave_live && lane < src.nv) {
+    // every wave has finished: the origin sums of all items and the table
+    // are complete
+    __syncthreads();
+    if (wave_live && lane < my_nv) {
         const float ox = ogr[wv][3 * lane], oy = ogr[wv][3 * lane + 1], oz = ogr[wv][3 * lane + 2];
         if (ox != 0.f || oy != 0.f || oz != 0.f) {
-            const int64_t j = __float_as_int(rec[kLeafF4 * (src.m0 + lane) + 2].w);
+            const int64_t j = __float_as_int(rec[kLeafF4 * (my_m0 + lane) + 2].w);
             unsafeAtomicAdd(gm + 3 * j + 0, ox);
             unsafeAtomicAdd(gm + 3 * j + 1, oy);
             unsafeAtomicAdd(gm + 3 * j + 2, oz);
         }
     }
     // the block's table: one set of global atomics per Gaussian
-    __syncthreads();
     for (int s = threadIdx.x; s < kHashSlots; s += kTraceBlock) {
         const int64_t j = table.key[s];
         if (j < 0) continue;
