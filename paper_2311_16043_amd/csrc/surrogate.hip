@@ -613,13 +613,15 @@ __global__ void k_store_count(const unsigned long long *__restrict__ count, int6
     if (threadIdx.x == 0) *out = (int64_t)*count;
 }
 
-// Fallback list in the BVH's leaf (Morton) order: one wave per sorted leaf m
-// appends the flagged queries of Gaussian i = src(m) that lie in the range
-// [q_begin, q_begin + q_count), as positions s = q - q_begin in increasing
-// order, after one atomic reservation per Gaussian. Rays of nearby Gaussians
-// then sit together in the list, so the tracer's concurrent pools share the
-// part of the tree in cache. The list order between Gaussians depends on
-// scheduling; each ray's result does not.
+// Fallback list in the BVH's leaf (Morton) order, direction by direction:
+// one wave per group of 64 consecutive sorted positions (lane l holds
+// Gaussian i = src(64 g + l)) appends the group's flagged queries that lie
+// in [q_begin, q_begin + q_count) as positions s = q - q_begin, direction k
+// by direction k and lane by lane within a direction, after one atomic
+// reservation per group. A pool of consecutive list entries then holds rays
+// of nearby Gaussians in the same few directions, which walk the same part of
+// the tree together. The list order between groups depends on scheduling;
+// each ray's result does not.
 __global__ __launch_bounds__(256) void k_fallback_rows(const float4 *__restrict__ rec, int64_t n, int K,
                                                        int64_t q_begin, int64_t q_count,
                                                        const uint8_t *__restrict__ flag,
@@ -628,24 +630,34 @@ __global__ __launch_bounds__(256) void k_fallback_rows(const float4 *__restrict_
     const int lane = threadIdx.x & 63;
     const uint64_t lt = (1ull << lane) - 1ull;
     const int64_t q_end = q_begin + q_count;
-    for (int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); m < n; m += (int64_t)gridDim.x * 4) {
-        const int64_t i = __float_as_int(rec[kLeafF4 * m + 2].w);
-        const int64_t lo = max(i * K, q_begin) - q_begin, hi = min((i + 1) * K, q_end) - q_begin;
-        if (lo >= hi) continue;  // wave-uniform
+    const int64_t n_groups = (n + 63) / 64;
+    for (int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); grp < n_groups; grp += (int64_t)gridDim.x * 4) {
+        const int64_t m = grp * 64 + lane;
+        // this lane's Gaussian and the directions of it that lie in the range
+        int64_t row = 0;  // s of direction 0
+        int k_lo = 0, k_hi = 0;
+        if (m < n) {
+            const int64_t i = __float_as_int(rec[kLeafF4 * m + 2].w);
+            row = i * K - q_begin;
+            // clamped to [0, K] in 64 bits: rows far outside the range give k_lo >= k_hi
+            k_lo = (int)min<int64_t>(K, max<int64_t>(0, -row));
+            k_hi = (int)max<int64_t>(0, min<int64_t>(K, q_count - row));
+        }
+        const bool any = __ballot(k_lo < k_hi) != 0;
+        if (!any) continue;  // wave-uniform
         int total = 0;
-        for (int64_t s0 = lo; s0 < hi; s0 += 64) {
-            const int64_t s = s0 + lane;
-            total += __popcll(__ballot(s < hi && flag[s] != 0));
+        for (int k = 0; k < K; ++k) {
+            const bool f = k >= k_lo && k < k_hi && flag[row + k] != 0;
+            total += __popcll(__ballot(f));
         }
         if (total == 0) continue;
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(count, (unsigned long long)total);
         base = __shfl(base, 0);
-        for (int64_t s0 = lo; s0 < hi; s0 += 64) {
-            const int64_t s = s0 + lane;
-            const bool f = s < hi && flag[s] != 0;
+        for (int k = 0; k < K; ++k) {
+            const bool f = k >= k_lo && k < k_hi && flag[row + k] != 0;
             const uint64_t b = __ballot(f);
-            if (f) list[base + __popcll(b & lt)] = s;
+            if (f) list[base + __popcll(b & lt)] = row + k;
             base += __popcll(b);
         }
     }
@@ -936,7 +948,7 @@ extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, con
         const Cuts c = make_cuts(*p);
         // the compacted fallback list holds positions s; the ray is q_begin + s
         const BvhLayout BL = bvh_layout(g->n);
-        const int64_t rows_blocks = std::min<int64_t>((g->n + 3) / 4, int64_t(1) << 16);
+        const int64_t rows_blocks = std::min<int64_t>(((g->n + 63) / 64 + 3) / 4, int64_t(1) << 16);
         hipLaunchKernelGGL(k_fallback_rows, dim3((unsigned)rows_blocks), dim3(256), 0, s, at<float4>(bvh, BL.leaf_rec),
                            g->n, (int)K, q_begin, q_count, flag, count, list);
         launch_trace_list(bvh, g, dirs, K, c, (const int64_t *)list, q_count, (const unsigned long long *)count,
