@@ -135,6 +135,23 @@ def test_long_ray_list_in_runs_matches_full_trace_bitwise():
     assert bad == 0
 
 
+def test_mean_without_per_ray_output_is_the_same():
+    """Without per-ray output the rows go through the workspace; the means must
+    equal those computed next to the per-ray output, bit for bit."""
+    sc = scenes.make_object_scene(30_000, 1)
+    dirs = scenes.fibonacci_dirs(77, True)
+    g = Gaussians.from_scene(sc)
+    bvh = build_bvh(g)
+    vr, vm = trace_visibility(bvh, g, dirs)
+    none, vm2 = trace_visibility(bvh, g, dirs, want_ray=False)
+    torch.cuda.synchronize()
+    assert none is None
+    assert torch.equal(vm, vm2)
+    # and they are the row means of the per-ray values
+    ref = vr.double().mean(1).float()
+    assert torch.max(torch.abs(vm - ref)).item() <= 1e-6
+
+
 def test_trace_is_deterministic():
     sc = scenes.make_object_scene(30_000, 1)
     dirs = scenes.fibonacci_dirs(64, True)
