@@ -1,13 +1,19 @@
-"""Launch sizes past the 32-bit work-item count of one dispatch: inference over
-more than 2^31 queries and an all-ray trace over more than 2^32 lane-rays are
-split into several grids, and every output is still written and equal to what
-the single-ray entry points give for the same rays."""
+"""The largest sizes: inference over more than 2^31 queries (split into
+several grids, since a dispatch counts its work-items in 32 bits), an all-ray
+trace over more than 2^32 rays (one persistent grid whose pool indices pass
+2^32 rays' worth, with the rows of the means in an 18 GB workspace), and the
+surrogate-scale workload (3M Gaussians x 1,024 directions) against the FP64
+oracle. Every output is written and equal to what the single-ray entry points
+give for the same rays."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2311_16043_amd import Gaussians, Surrogate, TraceParams, build_bvh, ray_setup, trace_rays, trace_visibility
 from workloads import scenes
+
+from _parity import check_vis
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +43,7 @@ def test_surrogate_grid_beyond_2_31_queries():
 
 
 def test_trace_beyond_2_32_lane_rays():
-    n, K = 4_400_000, 1024                      # 4.5e9 rays: 17.2M pooled waves, two launches
+    n, K = 4_400_000, 1024                      # 4.5e9 rays
     print(f"[large] trace n={n} K={K}", flush=True)
     sc = scenes.make_cube_cloud(n, 0)
     dirs = scenes.fibonacci_dirs(K, False)
@@ -46,8 +52,8 @@ def test_trace_beyond_2_32_lane_rays():
     bvh = build_bvh(g)
     _, vm = trace_visibility(bvh, g, dirs, prm, want_ray=False)
     torch.cuda.synchronize()
-    # Gaussians first and last in sorted order (the first and the second launch)
-    # and a random sample: their means from the ray-list kernel
+    # Gaussians first and last in sorted order (the first and the last XCD
+    # queue) and a random sample: their means from the ray-list kernel
     perm = bvh.arrays()["perm"].astype(np.int64)
     sample = np.concatenate([perm[:64], perm[-64:], np.random.default_rng(2).integers(0, n, 64)])
     ids = (sample[:, None] * K + np.arange(K)[None, :]).reshape(-1)
@@ -55,4 +61,29 @@ def test_trace_beyond_2_32_lane_rays():
     want = (T.sum(1) / K).astype(np.float32)
     got = vm.cpu().numpy()[sample]
     assert np.all(np.isfinite(got))
+    assert np.all(np.abs(got - want) <= 2 * np.spacing(np.abs(want))), np.abs(got - want).max()
+
+
+def test_surrogate_scale_full_size_sampled():
+    """3M Gaussians (20 objects) x 1,024 hemisphere directions, traced as the
+    bench traces it; 96 seeded rays against the brute-force FP64 oracle, and
+    the means of 8 Gaussians against their 1,024 rays."""
+    sc = scenes.make_scene("surrogate")
+    dirs = scenes.preset_dirs("surrogate")
+    n, K = sc["mean"].shape[0], dirs.shape[0]
+    print(f"[large] surrogate scale n={n} K={K}", flush=True)
+    prm = TraceParams()
+    g = Gaussians.from_scene(sc)
+    bvh = build_bvh(g)
+    _, vm = trace_visibility(bvh, g, dirs, prm, want_ray=False)
+    ids = scenes.sample_ray_ids(n, K, 96, seed=17)
+    vr = trace_rays(bvh, g, dirs, ids, prm).cpu().numpy()
+    orc = oracle.trace_rays(sc, dirs, 1, ids, oracle.params(alpha_min=1 / 255, alpha_max=0.99,
+                                                            sigma_cut=prm.sigma_cut, tmin_scale=prm.tmin_scale))
+    check_vis(vr, orc, label="surrogate-scale sampled")
+    sample = np.random.default_rng(18).integers(0, n, 8)
+    rows = (sample[:, None] * K + np.arange(K)[None, :]).reshape(-1)
+    T = trace_rays(bvh, g, dirs, rows, prm).cpu().numpy().astype(np.float64).reshape(-1, K)
+    want = (T.sum(1) / K).astype(np.float32)
+    got = vm.cpu().numpy()[sample]
     assert np.all(np.abs(got - want) <= 2 * np.spacing(np.abs(want))), np.abs(got - want).max()
