@@ -127,10 +127,11 @@ size_t rv_build_workspace_bytes(int64_t n);
  * significant in each triplet); stable LSD radix sort of (key, index);
  * binary radix tree with Karras 2012 node numbering (internal node i has one
  * end of its key range at i; the root is node 0; children are written as the
- * internal id, or ~m for leaf m); per-leaf records in sorted order; bottom-up
- * refit of the 3-sigma boxes. Node record (16 floats): left-child box lo[3],
- * hi[3], right-child box lo[3], hi[3], then the left and right child ids as
- * int32 bit patterns, then 2 unused words. Compressed four-wide record of
+ * internal id, or ~m for leaf m); per-leaf records in sorted order; refit of
+ * the 3-sigma boxes (each child box the union of the leaf boxes under it).
+ * Node record (16 floats): left-child box lo[3], hi[3], right-child box lo[3],
+ * hi[3], then the left and right child ids, then the first and last sorted
+ * leaf under the node, all four as int32 bit patterns. Compressed four-wide record of
  * internal node i (16 words, the one the tracer walks) lists the children of
  * i's two children; a leaf child keeps its own slot and the next slot is
  * empty. Words 0-2: origin O (float); word 3: bytes 0-2 per-axis step

@@ -294,7 +294,9 @@ __global__ __launch_bounds__(256) void k_karras(const uint64_t *__restrict__ key
     const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
     const int32_t left = (lo == gamma) ? ~(int32_t)gamma : (int32_t)gamma;
     const int32_t right = (hi == gamma + 1) ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
-    nodes[4 * i + 3] = make_float4(__int_as_float(left), __int_as_float(right), 0.0f, 0.0f);
+    // words 12-15: the children, then the first and last sorted leaf under i
+    nodes[4 * i + 3] = make_float4(__int_as_float(left), __int_as_float(right), __int_as_float((int32_t)lo),
+                                   __int_as_float((int32_t)hi));
     parent[left >= 0 ? left : (n - 1 + (int64_t)~left)] = (int32_t)i;
     parent[right >= 0 ? right : (n - 1 + (int64_t)~right)] = (int32_t)i;
     if (i == 0) parent[0] = -1;
@@ -305,62 +307,128 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, int6
     if (i < count) p[i] = v;
 }
 
-// ---- bottom-up refit -----------------------------------------------------------
+// ---- refit -------------------------------------------------------------------
+//
+// Every internal node covers a contiguous range of sorted leaves (Karras), so
+// the box of each child is the union of the leaf boxes over the child's range:
+// min and max are exact in any order, so this equals the bottom-up union of
+// the children's boxes, with no ordering between nodes to arrange. Unions of
+// blocks of kBoxBlock consecutive leaves keep long ranges short: a range reads
+// at most 2 kBoxBlock leaf boxes and its whole blocks' boxes.
 
-// Box of a child: a leaf's own box, or the union of an internal node's two
-// child slots (left: floats 0-5, right: floats 6-11 of its record).
-__device__ __forceinline__ void child_box(int32_t child, const float *__restrict__ leaf_box, const float *nodes,
-                                          float b[6]) {
-    if (child < 0) {
-        const float *lb = leaf_box + 6 * (int64_t)~child;
-#pragma unroll
-        for (int a = 0; a < 6; ++a) b[a] = lb[a];
-    } else {
-        const float *rec = nodes + 16 * (int64_t)child;
+// Running union (lo, hi) of boxes, and the wave-wide union by butterfly.
+struct BoxAcc {
+    float lo[3], hi[3];
+    __device__ __forceinline__ void reset() {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const float l0 = __hip_atomic_load(rec + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const float l1 = __hip_atomic_load(rec + 6 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const float h0 = __hip_atomic_load(rec + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const float h1 = __hip_atomic_load(rec + 9 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            b[a] = fminf(l0, l1);
-            b[3 + a] = fmaxf(h0, h1);
+            lo[a] = __builtin_inff();
+            hi[a] = -__builtin_inff();
+        }
+    }
+    __device__ __forceinline__ void add(const float *__restrict__ b) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], b[a]);
+            hi[a] = fmaxf(hi[a], b[3 + a]);
+        }
+    }
+    __device__ __forceinline__ void wave_union() {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fminf(lo[a], __shfl_xor(lo[a], off));
+                hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off));
+            }
+    }
+    __device__ __forceinline__ void store(float *__restrict__ out) const {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            out[a] = lo[a];
+            out[3 + a] = hi[a];
+        }
+    }
+};
+
+// block_box[b] = union of the leaf boxes of leaves b kBoxBlock .. (b + 1) kBoxBlock - 1
+// (one wave per block).
+__global__ __launch_bounds__(256) void k_block_boxes(int64_t n, const float *__restrict__ leaf_box,
+                                                     float *__restrict__ block_box) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nb = (n + kBoxBlock - 1) / kBoxBlock;
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += (int64_t)gridDim.x * 4) {
+        BoxAcc acc;
+        acc.reset();
+        const int64_t e = min(n, (b + 1) * kBoxBlock);
+        for (int64_t m = b * kBoxBlock + lane; m < e; m += 64) acc.add(leaf_box + 6 * m);
+        acc.wave_union();
+        if (lane == 0) acc.store(block_box + 6 * b);
+    }
+}
+
+// Union of the leaf boxes of sorted leaves [a, e) by one wave (result in
+// every lane).
+__device__ __forceinline__ void range_union(int64_t a, int64_t e, const float *__restrict__ leaf_box,
+                                            const float *__restrict__ block_box, int lane, BoxAcc &acc) {
+    acc.reset();
+    const int64_t ba = (a + kBoxBlock - 1) / kBoxBlock, be = e / kBoxBlock;  // whole blocks [ba, be)
+    if (ba >= be) {
+        for (int64_t m = a + lane; m < e; m += 64) acc.add(leaf_box + 6 * m);
+    } else {
+        for (int64_t m = a + lane; m < ba * kBoxBlock; m += 64) acc.add(leaf_box + 6 * m);
+        for (int64_t b = ba + lane; b < be; b += 64) acc.add(block_box + 6 * b);
+        for (int64_t m = be * kBoxBlock + lane; m < e; m += 64) acc.add(leaf_box + 6 * m);
+    }
+    acc.wave_union();
+}
+
+// Child boxes of every internal node (one wave per node): the left child
+// covers leaves [lo, gamma], the right [gamma + 1, hi], gamma being the left
+// child's last leaf; node 0's union is the root box in the header.
+__global__ __launch_bounds__(256) void k_refit_ranges(int64_t n, const float *__restrict__ leaf_box,
+                                                      const float *__restrict__ block_box, float *__restrict__ nodes,
+                                                      float *__restrict__ header) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n - 1; i += (int64_t)gridDim.x * 4) {
+        float *rec = nodes + 16 * i;
+        const int32_t left = __float_as_int(rec[12]);
+        const int64_t lo = __float_as_int(rec[14]), hi = __float_as_int(rec[15]);
+        // the split gamma is the left child's index, whether leaf (~gamma) or node
+        const int64_t gamma = left < 0 ? (int64_t)~left : (int64_t)left;
+        BoxAcc l, r;
+        range_union(lo, gamma + 1, leaf_box, block_box, lane, l);
+        range_union(gamma + 1, hi + 1, leaf_box, block_box, lane, r);
+        if (lane == 0) {
+            l.store(rec);
+            r.store(rec + 6);
+            if (i == 0) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    header[6 + a] = fminf(l.lo[a], r.lo[a]);
+                    header[9 + a] = fmaxf(l.hi[a], r.hi[a]);
+                }
+            }
         }
     }
 }
 
-// One thread per leaf walks towards the root. At each parent it stores its
-// child's box into the parent's record and bumps the parent's counter; the
-// first arrival stops, the second (which then sees both slots) continues.
-// Only node ids are carried from level to level; each level re-reads the
-// box it publishes.
-__global__ __launch_bounds__(256) void k_refit(int64_t n, const float *__restrict__ leaf_box,
-                                               const int32_t *__restrict__ parent, float *nodes,
-                                               uint32_t *flags, float *header) {
-    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
-    int32_t child = ~(int32_t)m;
-    int32_t node = parent[n - 1 + m];
-    // a valid tree has at most 95 internal levels; the bound only guards the loop
-    for (int level = 0; node >= 0 && level < 128; ++level) {
-        float b[6];
-        child_box(child, leaf_box, nodes, b);
-        float *rec = nodes + 16 * (int64_t)node;
-        const int32_t lc = __float_as_int(rec[12]);
-        float *slot = rec + (lc == child ? 0 : 6);
-#pragma unroll
-        for (int a = 0; a < 6; ++a) slot[a] = b[a];
-        // release our box, acquire the sibling's: device scope (all XCDs)
-        const uint32_t prev = __hip_atomic_fetch_add(flags + node, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == 0) return;  // first arrival: the sibling's thread continues
-        child = node;
-        node = parent[node];
-    }
-    if (node < 0) {
-        float b[6];
-        child_box(child, leaf_box, nodes, b);
-#pragma unroll
-        for (int a = 0; a < 6; ++a) header[6 + a] = b[a];
+// A single Gaussian: its leaf box is the root box.
+__global__ void k_root_single(const float *__restrict__ leaf_box, float *__restrict__ header) {
+    if (threadIdx.x < 6) header[6 + threadIdx.x] = leaf_box[threadIdx.x];
+}
+
+// Refit of a tree built over n sorted leaves (nodes hold their ranges).
+inline void launch_refit(int64_t n, const float *leaf_box, float *block_box, float *nodes, float *header,
+                         hipStream_t s) {
+    if (n > 1) {
+        const int64_t nb = (n + kBoxBlock - 1) / kBoxBlock;
+        hipLaunchKernelGGL(k_block_boxes, dim3((unsigned)std::min<int64_t>((nb + 3) / 4, 65536)), dim3(256), 0, s,
+                           n, leaf_box, block_box);
+        hipLaunchKernelGGL(k_refit_ranges, dim3((unsigned)std::min<int64_t>((n - 1 + 3) / 4, 65536)), dim3(256), 0,
+                           s, n, leaf_box, block_box, nodes, header);
+    } else {
+        hipLaunchKernelGGL(k_root_single, dim3(1), dim3(64), 0, s, leaf_box, header);
     }
 }
 
@@ -530,7 +598,7 @@ extern "C" rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
     uint32_t *vals_tmp = at<uint32_t>(ws, W.vals_tmp);
     uint32_t *hist = at<uint32_t>(ws, W.hist);
     float *bpart = at<float>(ws, W.bounds);
-    uint32_t *flags = at<uint32_t>(ws, W.flags);
+    float *block_box = at<float>(ws, W.block_box);
 
     const int nb = (int)std::min<int64_t>(kBoundsBlocks, (n + 255) / 256);
     hipLaunchKernelGGL(k_bounds_partial, dim3(nb), dim3(256), 0, s, g->mean, n, bpart);
@@ -560,14 +628,13 @@ extern "C" rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
     if (n > 1) {
         hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, keys, n,
                            reinterpret_cast<float4 *>(nodes), parent);
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, flags, n - 1, 0u);
-        hipLaunchKernelGGL(k_refit, dim3(grid_for(n, 256)), dim3(256), 0, s, n, box, parent, nodes, flags, header);
+        launch_refit(n, box, block_box, nodes, header, s);
         hipLaunchKernelGGL(k_collapse4, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, n, nodes, header,
                            at<float>(bvh, L.nodes4));
     } else {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(parent), (int64_t)1,
                            0xffffffffu);
-        hipLaunchKernelGGL(k_refit, dim3(1), dim3(64), 0, s, n, box, parent, nodes, flags, header);
+        launch_refit(n, box, block_box, nodes, header, s);
     }
     return check_launch("leaf records / karras / refit");
 }
@@ -591,12 +658,11 @@ extern "C" rv_status rv_refit_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
     float *header = at<float>(bvh, L.header);
     const uint32_t *perm = at<uint32_t>(bvh, L.perm);
     float *nodes = at<float>(bvh, L.nodes);
-    const int32_t *parent = at<int32_t>(bvh, L.parent);
     float4 *rec = at<float4>(bvh, L.leaf_rec);
     float *box = at<float>(bvh, L.leaf_box);
     float4 *orig = at<float4>(bvh, L.origins);
     float *bpart = at<float>(ws, W.bounds);
-    uint32_t *flags = at<uint32_t>(ws, W.flags);
+    float *block_box = at<float>(ws, W.block_box);
     // the scene scale of the leaf widening follows the moved means; the sorted
     // order, keys and topology stay as built
     const int nb = (int)std::min<int64_t>(kBoundsBlocks, (n + 255) / 256);
@@ -604,13 +670,9 @@ extern "C" rv_status rv_refit_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
     hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, bpart, nb, header, n);
     hipLaunchKernelGGL(k_leaf_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, g->mean, g->quat, g->log_scale,
                        g->opacity, g->normal, n, perm, header, rec, box, orig);
-    if (n > 1) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, flags, n - 1, 0u);
-        hipLaunchKernelGGL(k_refit, dim3(grid_for(n, 256)), dim3(256), 0, s, n, box, parent, nodes, flags, header);
+    launch_refit(n, box, block_box, nodes, header, s);
+    if (n > 1)
         hipLaunchKernelGGL(k_collapse4, dim3(grid_for(n - 1, 256)), dim3(256), 0, s, n, nodes, header,
                            at<float>(bvh, L.nodes4));
-    } else {
-        hipLaunchKernelGGL(k_refit, dim3(1), dim3(64), 0, s, n, box, parent, nodes, flags, header);
-    }
     return check_launch("rv_refit_bvh");
 }

@@ -77,8 +77,11 @@ constexpr int kSortItems = 32;
 constexpr int kSortTile = kSortWave * kSortItems;
 constexpr int kBoundsBlocks = 1024;
 
+// Leaves per block box of the refit (unions of consecutive sorted leaves).
+constexpr int64_t kBoxBlock = 256;
+
 struct BuildWsLayout {
-    size_t keys_tmp, vals_tmp, hist, bounds, flags, total;
+    size_t keys_tmp, vals_tmp, hist, bounds, block_box, total;
     int64_t nblocks;
 };
 
@@ -91,7 +94,7 @@ inline BuildWsLayout build_ws_layout(int64_t n) {
     W.vals_tmp = off; off = align_up(off + nn * 4);
     W.hist = off; off = align_up(off + 256 * (size_t)W.nblocks * 4);
     W.bounds = off; off = align_up(off + kBoundsBlocks * 6 * sizeof(float));
-    W.flags = off; off = align_up(off + nn * 4);
+    W.block_box = off; off = align_up(off + (size_t)((nn + kBoxBlock - 1) / kBoxBlock) * 6 * sizeof(float));
     W.total = off;
     return W;
 }
