@@ -135,26 +135,37 @@ __global__ __launch_bounds__(kSortWave) void k_sort_hist(const uint64_t *__restr
 
 // Exclusive prefix sum over hist[256 * nblocks] (digit-major) in one block.
 __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ hist, int64_t total) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t chunk = (total + 1023) / 1024;
-    const int64_t b = (int64_t)t * chunk, e = min(total, b + chunk);
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += hist[i];
-    part[t] = s;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
-    for (int w = 1; w < 1024; w <<= 1) {
-        uint32_t v = (t >= w) ? part[t - w] : 0u;
+    // exclusive prefix sum in place, 1024 consecutive counts at a time:
+    // coalesced loads, a shuffle scan per wave, the 16 wave totals scanned in
+    // LDS, and a running carry between rows
+    __shared__ uint32_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < total; base += 1024) {
+        const int64_t i = base + t;
+        const uint32_t v = i < total ? hist[i] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
         __syncthreads();
-        part[t] += v;
+        if (w == 0) {
+            uint32_t u = lane < 16 ? wsum[lane] : 0u;
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const uint32_t y = __shfl_up(u, off);
+                if (lane >= off) u += y;
+            }
+            if (lane < 16) wsum[lane] = u;
+        }
         __syncthreads();
-    }
-    uint32_t run = part[t] - s;  // exclusive
-    for (int64_t i = b; i < e; ++i) {
-        uint32_t v = hist[i];
-        hist[i] = run;
-        run += v;
+        const uint32_t before = w > 0 ? wsum[w - 1] : 0u;
+        if (i < total) hist[i] = carry + before + x - v;
+        carry += wsum[15];
+        __syncthreads();  // wsum is rewritten by the next row
     }
 }
 
