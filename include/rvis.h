@@ -208,7 +208,7 @@ rv_status rv_trace_rays(const void *bvh, const rv_gaussians *g, const float *dir
 /*
  * Bytes of the workspace of rv_trace_visibility_sh: 256 bytes of queue
  * counters, the K x 9 table of Y_j(d_k), and the per-ray values of one batch
- * of Gaussians (at most 2^26 values, 256 MB, however large n is).
+ * of Gaussians (at most 2^28 values, 1 GiB, however large n is).
  */
 size_t rv_trace_sh_workspace_bytes(int64_t n, int32_t K);
 

@@ -153,24 +153,37 @@ struct RaySetup {
     int64_t out;        // output position of its T
 };
 
-// Pools handed to one wave. XcdQueue: the pools [begin, end) of the wave's
-// XCD, taken one at a time through an atomic counter that all waves on that
-// XCD share (the counter starts at zero); every wave keeps taking until the
-// range is spent, so each XCD's waves finish together. RangeQueue: a fixed
-// run of consecutive pools.
+// Pools handed to one wave. XcdQueue: the pools are cut into kXcds
+// contiguous ranges, one per XCD, each drained one pool at a time through an
+// atomic counter (zero at launch). A wave takes from its own XCD's range
+// first, so that adjacent Gaussians share that XCD's L2; once the range is
+// spent it takes from the other ranges in turn, so no XCD idles while another
+// still holds work. RangeQueue: a fixed run of consecutive pools.
 struct XcdQueue {
-    unsigned long long *ctr;
-    int64_t begin, end;
-    // Next pool in p, false once the range is spent. Called in wave-uniform
+    unsigned long long *ctrs;  // kXcds counters
+    int64_t n_pools;
+    int home, turn;  // the range being drained is (home + turn) % kXcds
+    __device__ __forceinline__ void init(unsigned long long *c, int64_t np, int x) {
+        ctrs = c;
+        n_pools = np;
+        home = x;
+        turn = 0;
+    }
+    // Next pool in p, false once every range is spent. Called in wave-uniform
     // control flow; the first active lane takes the pool for the wave.
     __device__ __forceinline__ bool take(int64_t &p) {
         const int lane = threadIdx.x & 63;
-        unsigned long long t = 0;
-        if (lane == __builtin_amdgcn_readfirstlane(lane)) t = atomicAdd(ctr, 1ull);
-        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t);
-        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(t >> 32));
-        p = begin + (int64_t)(((uint64_t)hi << 32) | lo);
-        return p < end;
+        while (turn < kXcds) {
+            const int x = (home + turn) % kXcds;
+            unsigned long long t = 0;
+            if (lane == __builtin_amdgcn_readfirstlane(lane)) t = atomicAdd(ctrs + x, 1ull);
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(t >> 32));
+            p = n_pools * x / kXcds + (int64_t)(((uint64_t)hi << 32) | lo);
+            if (p < n_pools * (x + 1) / kXcds) return true;
+            ++turn;
+        }
+        return false;
     }
 };
 
@@ -430,9 +443,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__re
     pools.inv_nv = 1.0f;
     const int64_t n_pools = ((m_hi - m_lo + 63) / 64) * (int64_t)pools.n_chunks;
     XcdQueue q;
-    q.ctr = queues + x;
-    q.begin = n_pools * x / kXcds;
-    q.end = n_pools * (x + 1) / kXcds;
+    q.init(queues, n_pools, x);
     int64_t cn = 0, cl = 0, ch = 0;
     stream_rays<kCount>(nodes4, rec, c, n, q, pools, stk + threadIdx.x, fifo + threadIdx.x, vis_ray, cn, cl, ch);
     if (kCount) {
@@ -464,10 +475,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_list(
     using Queue = typename std::conditional<kQueue, XcdQueue, RangeQueue>::type;
     Queue q;
     if constexpr (kQueue) {
-        const int x = (int)(blockIdx.x % kXcds);
-        q.ctr = queues + x;
-        q.begin = n_pools * x / kXcds;
-        q.end = n_pools * (x + 1) / kXcds;
+        q.init(queues, n_pools, (int)(blockIdx.x % kXcds));
     } else {
         const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
         q.next = w * run;
@@ -519,8 +527,8 @@ __global__ __launch_bounds__(256) void k_mean_rows(const float *__restrict__ vis
 // kernel into a bounded buffer of rows, and each row is projected in FP64 in a
 // fixed order (deterministic).
 constexpr int kShCoef = 9;
-// Per-ray values held per batch: at most 2^26 (256 MB).
-constexpr int64_t kShBatchRays = int64_t(1) << 26;
+// Per-ray values held per batch: at most 2^28 (1 GiB).
+constexpr int64_t kShBatchRays = int64_t(1) << 28;
 
 // Gaussians per batch: a multiple of 64, at least 64, at most n.
 inline int64_t sh_batch(int64_t n, int K) {

@@ -154,10 +154,10 @@ def test_sh_workspace_and_rejects_bad_arguments(lib):
     for n, K in ((1, 1), (10, 8), (1000, 256), (300_000, 256), (3_000_000, 1024)):
         b = lib.rv_trace_sh_workspace_bytes(n, K)
         # queue counters, the K x 9 table and one batch of per-ray values
-        # (all n rows up to 2^26 values, never more than 2^26 + a table)
-        rows = min(n * K, 1 << 26)
+        # (all n rows up to 2^28 values, never more than 2^28 + a table)
+        rows = min(n * K, 1 << 28)
         assert b % 256 == 0 and b >= 256 + K * 9 * 4 + rows * 4 and b >= prev
-        assert b <= 256 + K * 9 * 4 + (1 << 26) * 4 + 1024
+        assert b <= 256 + K * 9 * 4 + (1 << 28) * 4 + 1024
         prev = b
     P = 1 << 40
     g = _g()
