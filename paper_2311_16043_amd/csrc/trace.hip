@@ -10,8 +10,10 @@
 // consecutive entries for the list kernel. The all-ray forward runs a
 // persistent grid that takes pools from eight queues, one per XCD, each a
 // contiguous eighth of the Morton order, so each L2 sees a compact part of the
-// tree; a wave keeps its lanes supplied across pool boundaries, so the skewed
-// per-ray work leaves lanes idle only in a wave's last pool. Each ray writes
+// tree; a wave whose queue is spent takes pools from the others, so no XCD
+// idles while another still holds work. A wave keeps its lanes supplied
+// across pool boundaries, refilling idle lanes a dozen at a time, so the
+// skewed per-ray work leaves lanes idle mainly in a wave's last pool. Each ray writes
 // its own T; per-Gaussian means are FP64 row sums in a fixed order
 // (deterministic, no atomics).
 #include <atomic>
@@ -202,9 +204,10 @@ struct RangeQueue {
 };
 
 // Trace the rays of the pools the queue hands out with the lanes of one
-// wave. A lane without a ray takes the next ray of the current pool; when the
-// pool is spent the wave takes the next pool at once, so lanes stay supplied
-// across pool boundaries and only idle in the wave's last pool. A finished
+// wave. Once kRefillMin lanes are without a ray (or no lane has one), those
+// lanes take the next rays of the current pool; when the pool is spent the
+// wave takes the next pool at once, so lanes stay supplied across pool
+// boundaries. A finished
 // ray writes its T to out[r.out] (when out is given). stk and my_fifo are
 // this lane's columns of the block's LDS stack ring and leaf FIFO.
 template <bool kCount, class Queue, class Pools>
@@ -422,7 +425,8 @@ struct ListPools : ListSource {
 // for [0, n)) through per-XCD queues of pools. The grid is persistent (a
 // multiple of 8 blocks, about what the device holds at once) and block b
 // serves the queue of XCD b % 8 (round-robin dispatch), whose range is a
-// contiguous eighth of the pools: each L2 sees a compact part of the tree.
+// contiguous eighth of the pools: each L2 sees a compact part of the tree
+// until its range is spent and its waves help with the other ranges.
 template <bool kCount>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__restrict__ nodes4,
                                                               const float4 *__restrict__ rec,
@@ -467,7 +471,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__re
 // out_by_value: T goes to out[ids[j]] (the list holds output positions, the
 // ray being id_offset + ids[j]); otherwise to out[j]. With kQueue the grid is
 // persistent and takes pools from per-XCD queues (queues[8], zero at launch),
-// each a contiguous eighth of the list; otherwise wave w takes the run of
+// each a contiguous eighth of the list, stealing from the others once its own
+// is spent; otherwise wave w takes the run of
 // pools [w R, (w + 1) R).
 template <bool kQueue>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_list(
