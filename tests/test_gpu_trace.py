@@ -193,6 +193,25 @@ def test_single_gaussian_and_single_direction():
     assert np.array_equal(vr[:, 0], vm)
 
 
+@pytest.mark.parametrize("n,K,mode", [(130, 2, 1), (70, 5, 1), (190, 3, 0), (1000, 1, 0)])
+def test_fewer_pools_than_queue_ranges(n, K, mode):
+    """6 to 16 pools over the eight queue ranges, ragged last groups: waves
+    whose range is empty or spent take pools from the others, and lanes are
+    refilled in batches from partial pools. Every ray against the oracle, and
+    the ray-list kernel over all rays gives the same bits."""
+    sc = scenes.make_object_scene(n, 1) if mode else scenes.make_cube_cloud(n, 0)
+    dirs = scenes.fibonacci_dirs(K, bool(mode))
+    prm = TraceParams(dir_mode=mode)
+    g, bvh, vr, vm = _run(sc, dirs, prm)
+    orc = oracle.trace_all(sc, dirs, mode, _oprm(prm))
+    check_vis(vr.reshape(-1), orc, label=f"n={n} K={K}")
+    ids = np.arange(n * K, dtype=np.int64)
+    got = trace_rays(bvh, g, dirs, ids, prm).cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), vr.reshape(-1).view(np.uint32))
+    ref = (vr.astype(np.float64).sum(1) / K).astype(np.float32)
+    assert np.max(np.abs(vm - ref)) <= 1e-7
+
+
 def test_stats_are_consistent():
     sc = scenes.make_object_scene(20_000, 1)
     dirs = scenes.fibonacci_dirs(32, True)
