@@ -9,7 +9,9 @@
 //                                 wave64 ballot ranking, one wave per tile
 //   leaf_prep                     per sorted leaf: whitening W, 3-sigma box, origin data
 //   karras                        internal nodes and parents, one thread per node
-//   fill_u32 + refit              bottom-up box union, second arrival continues
+//   block_boxes + refit_ranges    each child box the union of the leaf boxes of
+//                                 its sorted-leaf range (no ordering between nodes)
+//   collapse4                     compressed four-wide records the tracer walks
 #include "rv_internal.h"
 
 namespace rv {
@@ -47,8 +49,10 @@ __global__ __launch_bounds__(256) void k_bounds_partial(const float *__restrict_
     if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
 }
 
+// check != 0 (refit): leave the header untouched unless it records n.
 __global__ __launch_bounds__(256) void k_bounds_final(const float *__restrict__ partial, int nparts,
-                                                      float *__restrict__ header, int64_t n) {
+                                                      float *__restrict__ header, int64_t n, int check) {
+    if (check && !tree_matches(header, n)) return;  // block-uniform
     __shared__ float s[6][256];
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     for (int b = threadIdx.x; b < nparts; b += 256) {
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(256) void k_leaf_prep(const float *__restrict__ mea
                                                    float4 *__restrict__ rec, float *__restrict__ box,
                                                    float4 *__restrict__ origins) {
     int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
+    if (m >= n || !tree_matches(header, n)) return;
     // scene scale: largest coordinate magnitude plus the diagonal of the means' box
     float scale = 0.0f, diag2 = 0.0f;
 #pragma unroll
@@ -365,7 +369,8 @@ struct BoxAcc {
 // block_box[b] = union of the leaf boxes of leaves b kBoxBlock .. (b + 1) kBoxBlock - 1
 // (one wave per block).
 __global__ __launch_bounds__(256) void k_block_boxes(int64_t n, const float *__restrict__ leaf_box,
-                                                     float *__restrict__ block_box) {
+                                                     float *__restrict__ block_box, const float *__restrict__ header) {
+    if (!tree_matches(header, n)) return;
     const int lane = threadIdx.x & 63;
     const int64_t nb = (n + kBoxBlock - 1) / kBoxBlock;
     for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += (int64_t)gridDim.x * 4) {
@@ -400,6 +405,7 @@ __device__ __forceinline__ void range_union(int64_t a, int64_t e, const float *_
 __global__ __launch_bounds__(256) void k_refit_ranges(int64_t n, const float *__restrict__ leaf_box,
                                                       const float *__restrict__ block_box, float *__restrict__ nodes,
                                                       float *__restrict__ header) {
+    if (!tree_matches(header, n)) return;
     const int lane = threadIdx.x & 63;
     for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n - 1; i += (int64_t)gridDim.x * 4) {
         float *rec = nodes + 16 * i;
@@ -426,6 +432,7 @@ __global__ __launch_bounds__(256) void k_refit_ranges(int64_t n, const float *__
 
 // A single Gaussian: its leaf box is the root box.
 __global__ void k_root_single(const float *__restrict__ leaf_box, float *__restrict__ header) {
+    if (!tree_matches(header, 1)) return;
     if (threadIdx.x < 6) header[6 + threadIdx.x] = leaf_box[threadIdx.x];
 }
 
@@ -435,7 +442,7 @@ inline void launch_refit(int64_t n, const float *leaf_box, float *block_box, flo
     if (n > 1) {
         const int64_t nb = (n + kBoxBlock - 1) / kBoxBlock;
         hipLaunchKernelGGL(k_block_boxes, dim3((unsigned)std::min<int64_t>((nb + 3) / 4, 65536)), dim3(256), 0, s,
-                           n, leaf_box, block_box);
+                           n, leaf_box, block_box, header);
         hipLaunchKernelGGL(k_refit_ranges, dim3((unsigned)std::min<int64_t>((n - 1 + 3) / 4, 65536)), dim3(256), 0,
                            s, n, leaf_box, block_box, nodes, header);
     } else {
@@ -467,7 +474,7 @@ inline void launch_refit(int64_t n, const float *leaf_box, float *block_box, flo
 __global__ __launch_bounds__(256) void k_collapse4(int64_t n, const float *__restrict__ nodes,
                                                    const float *__restrict__ header, float *__restrict__ nodes4) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
+    if (i >= n - 1 || !tree_matches(header, n)) return;
     double ext = 0.0, diag2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -613,7 +620,7 @@ extern "C" rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
 
     const int nb = (int)std::min<int64_t>(kBoundsBlocks, (n + 255) / 256);
     hipLaunchKernelGGL(k_bounds_partial, dim3(nb), dim3(256), 0, s, g->mean, n, bpart);
-    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, bpart, nb, header, n);
+    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, bpart, nb, header, n, 0);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, 256)), dim3(256), 0, s, g->mean, n, header, keys, perm);
     rv_status st = check_launch("morton");
     if (st != RV_OK) return st;
@@ -678,7 +685,7 @@ extern "C" rv_status rv_refit_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
     // order, keys and topology stay as built
     const int nb = (int)std::min<int64_t>(kBoundsBlocks, (n + 255) / 256);
     hipLaunchKernelGGL(k_bounds_partial, dim3(nb), dim3(256), 0, s, g->mean, n, bpart);
-    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, bpart, nb, header, n);
+    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, bpart, nb, header, n, 1);
     hipLaunchKernelGGL(k_leaf_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, g->mean, g->quat, g->log_scale,
                        g->opacity, g->normal, n, perm, header, rec, box, orig);
     launch_refit(n, box, block_box, nodes, header, s);

@@ -123,6 +123,15 @@ __device__ __forceinline__ f3 cross(f3 a, f3 b) {
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Header word 12 of a BVH blob holds the number of Gaussians it was built
+// over. Every kernel that reads a tree compares it with the caller's n before
+// touching anything else in the blob (the section offsets follow from n), so a
+// blob built for another Gaussian set is never walked: traversals give NaN and
+// a refit leaves the blob as it was.
+__device__ __forceinline__ bool tree_matches(const float *__restrict__ header, int64_t n) {
+    return __float_as_int(header[12]) == (int)(n & 0x7fffffff);
+}
+
 // Mask of the lanes whose `digit` equals this lane's, among `valid` lanes
 // (eight ballots, one per digit bit).
 __device__ __forceinline__ uint64_t match_digit8(uint32_t digit, uint64_t valid) {

@@ -622,7 +622,8 @@ __global__ void k_store_count(const unsigned long long *__restrict__ count, int6
 // of nearby Gaussians in the same few directions, which walk the same part of
 // the tree together. The list order between groups depends on scheduling;
 // each ray's result does not.
-__global__ __launch_bounds__(256) void k_fallback_rows(const float4 *__restrict__ rec, int64_t n, int K,
+__global__ __launch_bounds__(256) void k_fallback_rows(const float *__restrict__ header,
+                                                       const float4 *__restrict__ rec, int64_t n, int K,
                                                        int64_t q_begin, int64_t q_count,
                                                        const uint8_t *__restrict__ flag,
                                                        unsigned long long *__restrict__ count,
@@ -631,13 +632,16 @@ __global__ __launch_bounds__(256) void k_fallback_rows(const float4 *__restrict_
     const uint64_t lt = (1ull << lane) - 1ull;
     const int64_t q_end = q_begin + q_count;
     const int64_t n_groups = (n + 63) / 64;
+    // with a tree built for another Gaussian set the records are not read:
+    // Gaussians are taken in index order (the traversal then gives NaN)
+    const bool tree_ok = tree_matches(header, n);
     for (int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); grp < n_groups; grp += (int64_t)gridDim.x * 4) {
         const int64_t m = grp * 64 + lane;
         // this lane's Gaussian and the directions of it that lie in the range
         int64_t row = 0;  // s of direction 0
         int k_lo = 0, k_hi = 0;
         if (m < n) {
-            const int64_t i = __float_as_int(rec[kLeafF4 * m + 2].w);
+            const int64_t i = tree_ok ? (int64_t)__float_as_int(rec[kLeafF4 * m + 2].w) : m;
             row = i * K - q_begin;
             // clamped to [0, K] in 64 bits: rows far outside the range give k_lo >= k_hi
             k_lo = (int)min<int64_t>(K, max<int64_t>(0, -row));
@@ -949,7 +953,8 @@ extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, con
         // the compacted fallback list holds positions s; the ray is q_begin + s
         const BvhLayout BL = bvh_layout(g->n);
         const int64_t rows_blocks = std::min<int64_t>(((g->n + 63) / 64 + 3) / 4, int64_t(1) << 16);
-        hipLaunchKernelGGL(k_fallback_rows, dim3((unsigned)rows_blocks), dim3(256), 0, s, at<float4>(bvh, BL.leaf_rec),
+        hipLaunchKernelGGL(k_fallback_rows, dim3((unsigned)rows_blocks), dim3(256), 0, s, at<float>(bvh, BL.header),
+                           at<float4>(bvh, BL.leaf_rec),
                            g->n, (int)K, q_begin, q_count, flag, count, list);
         launch_trace_list(bvh, g, dirs, K, c, (const int64_t *)list, q_count, (const unsigned long long *)count,
                           q_begin, true, vis, queues, s);

@@ -374,12 +374,13 @@ struct ListSource {
     int64_t id_offset, base;
     double inv_k;  // 1 / K
     bool out_by_value;
+    bool tree_ok;  // the tree was built over these n Gaussians (else every ray is NaN)
     __device__ __forceinline__ RaySetup operator()(int idx) const {
         RaySetup r;
         const int64_t entry = ids[base + idx];
         const int64_t rid = entry + id_offset;
         r.out = out_by_value ? entry : base + idx;
-        r.valid = rid >= 0 && rid < n * (int64_t)K;
+        r.valid = tree_ok && rid >= 0 && rid < n * (int64_t)K;
         // rid / K from the FP64 quotient (off by at most one for rid < 2^52,
         // where rid converts exactly), corrected so that 0 <= k < K; integer
         // division beyond
@@ -428,7 +429,8 @@ struct ListPools : ListSource {
 // contiguous eighth of the pools: each L2 sees a compact part of the tree
 // until its range is spent and its waves help with the other ranges.
 template <bool kCount>
-__global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__restrict__ nodes4,
+__global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float *__restrict__ header,
+                                                              const float4 *__restrict__ nodes4,
                                                               const float4 *__restrict__ rec,
                                                               const float4 *__restrict__ origins,
                                                               const float *__restrict__ dirs, int64_t n, int K,
@@ -438,6 +440,16 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__re
                                                               unsigned long long *__restrict__ totals) {
     __shared__ int32_t stk[kStreamRing * kTraceBlock];
     __shared__ int32_t fifo[kFifo * kTraceBlock];
+    if (!tree_matches(header, n)) {
+        // a tree built for another Gaussian set: every ray of the range is NaN
+        if (vis_ray) {
+            const int64_t rows = (m_hi - m_lo) * (int64_t)K;
+            for (int64_t r = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; r < rows;
+                 r += (int64_t)gridDim.x * kTraceBlock)
+                vis_ray[r] = __int_as_float(0x7fc00000);
+        }
+        return;
+    }
     const int x = (int)(blockIdx.x % kXcds);
     GridPools pools;
     pools.rec = rec;
@@ -476,7 +488,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_stream(const float4 *__re
 // pools [w R, (w + 1) R).
 template <bool kQueue>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_list(
-    const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float *__restrict__ mean,
+    const float *__restrict__ header, const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float *__restrict__ mean,
     const float *__restrict__ normal, const float *__restrict__ log_scale, int64_t n, const float *__restrict__ dirs,
     int K, Cuts c, const int64_t *__restrict__ ids, int64_t n_list, const unsigned long long *__restrict__ count,
     int64_t id_offset, int out_by_value, int64_t run, unsigned long long *__restrict__ queues,
@@ -511,6 +523,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_list(
     pools.inv_k = 1.0 / (double)K;
     pools.out_by_value = out_by_value != 0;
     pools.total = total;
+    pools.tree_ok = tree_matches(header, n);
     int64_t cn = 0, cl = 0, ch = 0;
     stream_rays<false>(nodes4, rec, c, n, q, pools, stk + threadIdx.x, fifo + threadIdx.x, out, cn, cl, ch);
 }
@@ -582,10 +595,20 @@ __global__ __launch_bounds__(256) void k_sh_table(const float *__restrict__ dirs
 // stride and a fixed butterfly; vis_sh and vis_mean go to the Gaussian's
 // original index.
 __global__ __launch_bounds__(256) void k_sh_rows(const float *__restrict__ rows, int64_t m_lo, int64_t n_rows, int K,
-                                                 const float *__restrict__ Y, const float4 *__restrict__ rec,
-                                                 double dw, float *__restrict__ vis_sh,
-                                                 float *__restrict__ vis_mean) {
+                                                 const float *__restrict__ Y, const float *__restrict__ header,
+                                                 const float4 *__restrict__ rec, int64_t n, double dw,
+                                                 float *__restrict__ vis_sh, float *__restrict__ vis_mean) {
     const int lane = threadIdx.x & 63;
+    if (!tree_matches(header, n)) {
+        // a tree built for another Gaussian set: NaN for the batch's rows,
+        // placed by row (the batches together cover every Gaussian)
+        for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n_rows; r += (int64_t)gridDim.x * 256) {
+#pragma unroll
+            for (int j = 0; j < kShCoef; ++j) vis_sh[(m_lo + r) * kShCoef + j] = __int_as_float(0x7fc00000);
+            if (vis_mean) vis_mean[m_lo + r] = __int_as_float(0x7fc00000);
+        }
+        return;
+    }
     for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n_rows; r += (int64_t)gridDim.x * 4) {
         const float *row = rows + r * K;
         double acc[kShCoef + 1];
@@ -676,7 +699,7 @@ struct GradScatter {
 // the block's LDS table). The source's own term (through the ray origin) is
 // summed per Gaussian in LDS and added once per wave.
 __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
-    const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float4 *__restrict__ origins,
+    const float *__restrict__ header, const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float4 *__restrict__ origins,
     const float *__restrict__ dirs, PoolMap pm, Cuts c, const float *__restrict__ grad_ray,
     const float *__restrict__ grad_mean_in, const float *__restrict__ vis_fwd, float *go, float *gm, float *gl) {
     __shared__ int32_t stk[kPoolRing * kTraceBlock];
@@ -689,6 +712,17 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     __shared__ int64_t item_m0[kWavesPerBlock];
     __shared__ int blk_next;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (!tree_matches(header, pm.n)) {
+        // a tree built for another Gaussian set: every gradient is NaN
+        const float nan = __int_as_float(0x7fc00000);
+        for (int64_t j = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; j < pm.n;
+             j += (int64_t)gridDim.x * kTraceBlock) {
+            go[j] = nan;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gm[3 * j + c] = gl[3 * j + c] = nan;
+        }
+        return;
+    }
     for (int s = threadIdx.x; s < kHashSlots; s += kTraceBlock) {
         table.key[s] = -1;
 #pragma unroll
@@ -930,7 +964,7 @@ void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs
         hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t *>(queues),
                            (int64_t)(2 * kXcds), 0u);
         hipLaunchKernelGGL(k_trace_list<true>, dim3((unsigned)stream_blocks(pools)), dim3(kTraceBlock), 0, stream,
-                           at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean,
+                           at<float>(bvh, L.header), at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean,
                            c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, c, ids, n_list, count,
                            id_offset, out_by_value ? 1 : 0, (int64_t)0, queues, out);
         return;
@@ -938,7 +972,8 @@ void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs
     const int64_t run = (pools + kListTargetWaves - 1) / kListTargetWaves;
     const int64_t waves = (pools + run - 1) / run;
     hipLaunchKernelGGL(k_trace_list<false>, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
-                       dim3(kTraceBlock), 0, stream, at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean,
+                       dim3(kTraceBlock), 0, stream, at<float>(bvh, L.header), at<float4>(bvh, L.nodes4),
+                       at<float4>(bvh, L.leaf_rec), g->mean,
                        c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, c, ids, n_list, count, id_offset,
                        out_by_value ? 1 : 0, run, (unsigned long long *)nullptr, out);
 }
@@ -968,7 +1003,7 @@ void launch_trace_stream(const void *bvh, const rv_gaussians *g, const float *di
     hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(queues),
                        (int64_t)(2 * kXcds), 0u);
     hipLaunchKernelGGL(k_trace_stream<kCount>, dim3((unsigned)stream_blocks(n_pools)), dim3(kTraceBlock), 0, s,
-                       at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, g->n,
+                       at<float>(bvh, L.header), at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, g->n,
                        K, c, m_lo, m_hi, by_leaf ? 1 : 0, queues, vis_ray, totals);
 }
 
@@ -1047,7 +1082,7 @@ extern "C" rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaus
         part.w_off = w0;
         const int64_t nb = (std::min(kLaunchWaves, pm.n_items - w0) + kWavesPerBlock - 1) / kWavesPerBlock;
         hipLaunchKernelGGL(k_trace_backward, dim3((unsigned)nb), dim3(kTraceBlock), 0, (hipStream_t)stream,
-                           at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs,
+                           at<float>(bvh, L.header), at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs,
                            part, c, grad_vis_ray, grad_vis_mean, vis_ray_fwd, grad_opacity, grad_mean, grad_log_scale);
     }
     return check_launch("rv_trace_visibility_backward");
@@ -1085,7 +1120,7 @@ extern "C" rv_status rv_trace_visibility_sh(const void *bvh, const rv_gaussians 
         launch_trace_stream<false>(bvh, g, dirs, K, c, ws, rows, nullptr, s, m_lo, m_hi, true);
         const int64_t blocks = std::min<int64_t>((m_hi - m_lo + 3) / 4, int64_t(1) << 20);
         hipLaunchKernelGGL(k_sh_rows, dim3((unsigned)blocks), dim3(256), 0, s, rows, m_lo, m_hi - m_lo, (int)K, Y,
-                           at<float4>(bvh, L.leaf_rec), dw, vis_sh, vis_mean);
+                           at<float>(bvh, L.header), at<float4>(bvh, L.leaf_rec), g->n, dw, vis_sh, vis_mean);
     }
     return check_launch("rv_trace_visibility_sh");
 }

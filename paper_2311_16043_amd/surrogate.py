@@ -7,7 +7,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .tracer import BVH, Gaussians, TraceParams, _alloc_bytes, _dirs, _stream_ptr
+from .tracer import BVH, Gaussians, TraceParams, _alloc_bytes, _dirs, _stream_ptr, check_pair
 
 _F32 = torch.float32
 
@@ -114,6 +114,8 @@ class Surrogate:
                    out_vis: torch.Tensor | None = None, out_unc: torch.Tensor | None = None,
                    workspace: torch.Tensor | None = None):
         """(vis, unc, n_fallback) over queries q = i*K + k in [q_begin, q_begin + q_count)."""
+        if bvh is not None:
+            check_pair(bvh, g, "Surrogate.infer_grid")
         params = params or TraceParams()
         d = _dirs(dirs, self.device)
         K = int(d.shape[0])

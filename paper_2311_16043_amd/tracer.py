@@ -126,6 +126,13 @@ class BVH:
         )
 
 
+def check_pair(bvh: BVH, g: Gaussians, fn: str) -> None:
+    """Raise unless `bvh` was built over a Gaussian set of g's size (the C
+    ABI derives every section offset of the blob from g.n)."""
+    if g.n != bvh.n:
+        raise ValueError(f"{fn}: the BVH was built over {bvh.n} Gaussians, g has {g.n}; rebuild it")
+
+
 def build_bvh(g: Gaussians, workspace: torch.Tensor | None = None) -> BVH:
     L = _lib.load()
     dev = g.mean.device
@@ -148,8 +155,7 @@ def refit_bvh(bvh: BVH, g: Gaussians, workspace: torch.Tensor | None = None) -> 
     """Refit `bvh` in place to the (moved) Gaussians it was built from: same
     topology and order, boxes and records recomputed."""
     L = _lib.load()
-    if g.n != bvh.n:
-        raise ValueError(f"refit_bvh: the BVH holds {bvh.n} Gaussians, g has {g.n}")
+    check_pair(bvh, g, "refit_bvh")
     dev = g.mean.device
     ws_bytes = L.rv_build_workspace_bytes(g.n)
     if workspace is None or workspace.numel() < ws_bytes:
@@ -164,6 +170,7 @@ def trace_visibility(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = 
                      want_ray: bool = True, want_mean: bool = True, out_ray: torch.Tensor | None = None,
                      out_mean: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
     """(vis_ray [n, K] or None, vis_mean [n] or None) for every ray (i, k)."""
+    check_pair(bvh, g, "trace_visibility")
     params = params or TraceParams()
     dev = g.mean.device
     d = _dirs(dirs, dev)
@@ -185,6 +192,7 @@ def trace_visibility_sh(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None
                         workspace: torch.Tensor | None = None):
     """(vis_sh [n, 9], vis_mean [n] or None): each Gaussian's visibility
     projected onto the degree-2 real SH, with no per-ray output."""
+    check_pair(bvh, g, "trace_visibility_sh")
     params = params or TraceParams()
     dev = g.mean.device
     d = _dirs(dirs, dev)
@@ -202,6 +210,7 @@ def trace_visibility_sh(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None
 
 def trace_rays(bvh: BVH, g: Gaussians, dirs, ray_ids, params: TraceParams | None = None) -> torch.Tensor:
     """T of each listed ray id r = i*K + k (same bits as trace_visibility)."""
+    check_pair(bvh, g, "trace_rays")
     params = params or TraceParams()
     dev = g.mean.device
     d = _dirs(dirs, dev)
@@ -215,6 +224,7 @@ def trace_rays(bvh: BVH, g: Gaussians, dirs, ray_ids, params: TraceParams | None
 
 def trace_stats(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = None) -> dict:
     """Totals over all rays: internal nodes visited, leaves tested, Gaussians included."""
+    check_pair(bvh, g, "trace_stats")
     params = params or TraceParams()
     dev = g.mean.device
     d = _dirs(dirs, dev)
@@ -231,6 +241,7 @@ def trace_visibility_backward(bvh: BVH, g: Gaussians, dirs, params: TraceParams 
                               grad_vis_ray: torch.Tensor | None = None, grad_vis_mean: torch.Tensor | None = None,
                               vis_ray_fwd: torch.Tensor | None = None):
     """(grad_opacity [n], grad_mean [n,3], grad_log_scale [n,3]) of the upstream gradients."""
+    check_pair(bvh, g, "trace_visibility_backward")
     params = params or TraceParams()
     dev = g.mean.device
     d = _dirs(dirs, dev)
@@ -263,3 +274,16 @@ def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
     if dst.numel() * dst.element_size() != nbytes:
         raise ValueError("stream_copy: size mismatch")
     _lib.call("rv_stream_copy", src.data_ptr(), dst.data_ptr(), nbytes, _stream_ptr(src.device))
+
+
+def gather_probe(table: torch.Tensor, rounds: int, blocks: int) -> torch.Tensor:
+    """Record-gather probe over `table` (a device tensor of 64-byte records):
+    blocks x 256 threads each read `rounds` records as three 16-byte loads at
+    hashed indices. Returns the sink (one word per thread)."""
+    nbytes = table.numel() * table.element_size()
+    if nbytes % 64:
+        raise ValueError("gather_probe: the table must hold whole 64-byte records")
+    sink = torch.empty(blocks * 256, dtype=torch.int32, device=table.device)
+    _lib.call("rv_gather_probe", table.data_ptr(), nbytes // 64, int(rounds), int(blocks), sink.data_ptr(),
+              _stream_ptr(table.device))
+    return sink

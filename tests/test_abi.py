@@ -218,3 +218,31 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         _lib.load()
+
+
+def test_wrappers_reject_a_tree_of_another_gaussian_set():
+    """Every Python entry point that takes a BVH checks that it was built over
+    a Gaussian set of the same size before calling the library (the C ABI
+    derives the blob's section offsets from g.n)."""
+    import numpy as np
+    import torch
+
+    from paper_2311_16043_amd import (BVH, Gaussians, Surrogate, refit_bvh, trace_rays, trace_stats,
+                                      trace_visibility, trace_visibility_backward, trace_visibility_sh)
+    n = 10
+    g = Gaussians(np.zeros((n, 3), np.float32), np.tile(np.float32([1, 0, 0, 0]), (n, 1)),
+                  np.full((n, 3), -3.0, np.float32), np.full(n, 0.5, np.float32),
+                  np.tile(np.float32([0, 0, 1]), (n, 1)), device="cpu")
+    bvh = BVH(torch.empty(0, dtype=torch.uint8), n + 1)
+    dirs = np.float32([[0, 0, 1]])
+    calls = [lambda: trace_visibility(bvh, g, dirs), lambda: trace_visibility_sh(bvh, g, dirs),
+             lambda: trace_rays(bvh, g, dirs, [0]), lambda: trace_stats(bvh, g, dirs),
+             lambda: trace_visibility_backward(bvh, g, dirs, grad_vis_mean=torch.zeros(n)),
+             lambda: refit_bvh(bvh, g)]
+    for call in calls:
+        with pytest.raises(ValueError, match="built over 11 Gaussians"):
+            call()
+    net = Surrogate.__new__(Surrogate)  # no blob needed: the check comes first
+    net.device = torch.device("cpu")
+    with pytest.raises(ValueError, match="built over 11 Gaussians"):
+        net.infer_grid(g, dirs, bvh=bvh)
