@@ -26,6 +26,13 @@
  *    reported after a failed launch) and rv_last_error() describes the cause.
  *  - Ray ids: ray r = i * K + k is direction k of Gaussian i (original, not
  *    sorted, order); ids are 64-bit.
+ *  - A BVH blob records the number of Gaussians it was built over (header
+ *    word 12), and every section offset follows from that number. Entry
+ *    points that take a blob and a Gaussian set compare the two on the device
+ *    before reading anything else in the blob: with a different g->n the
+ *    traversals write NaN to their per-ray, per-Gaussian and gradient
+ *    outputs, and rv_refit_bvh leaves the blob unchanged. The host cannot see
+ *    device memory without synchronising, so such a call still returns RV_OK.
  */
 #ifndef RVIS_H
 #define RVIS_H
@@ -252,6 +259,21 @@ rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, const float *di
  * Errors: RV_ERR_INVALID_ARG (null or misaligned pointers, bad size), RV_ERR_HIP.
  */
 rv_status rv_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/*
+ * Record-gather probe: the achievable rate of the traversal's memory access
+ * pattern, measured rather than assumed. table: device, n_records records of
+ * 64 bytes (16-byte aligned); each of blocks x 256 threads reads `rounds`
+ * records (a positive multiple of 4), each as three 16-byte loads of its
+ * first 48 bytes, at indices hashed independently per thread and round, so
+ * the lanes of a wave diverge as traversal lanes do; four records are in
+ * flight per thread. sink: device uint32 [blocks * 256], receives the XOR of
+ * what each thread read. Bytes gathered = 48 * rounds * blocks * 256.
+ * Errors: RV_ERR_INVALID_ARG (null or misaligned pointers, sizes out of
+ * range), RV_ERR_HIP.
+ */
+rv_status rv_gather_probe(const void *table, int64_t n_records, int32_t rounds, int32_t blocks, uint32_t *sink,
+                          void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Adjoint                                                                  */
