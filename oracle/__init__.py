@@ -91,6 +91,10 @@ def lib():
         L.or_onb.argtypes = [_d, _d, _d]
         L.or_make_ray.argtypes = [_d, _d, _d, C.c_int32, _d, C.c_int32, C.c_double, C.c_int64,
                                   _d, _d, C.POINTER(C.c_double)]
+        L.or_max_threads.argtypes = []
+        L.or_max_threads.restype = C.c_int32
+        L.or_set_threads.argtypes = [C.c_int32]
+        L.or_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -277,3 +281,12 @@ def make_ray(scene: dict, dirs, dir_mode: int, r: int, tmin_scale: float = TMIN_
     lib().or_make_ray(mean, nrm, ls, dirs.shape[0], dirs.reshape(-1), int(dir_mode), tmin_scale, int(r),
                       o, d, C.byref(tm))
     return o, d, tm.value
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(lib().or_max_threads())
+
+
+def set_threads(t: int) -> None:
+    lib().or_set_threads(int(t))

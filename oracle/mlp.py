@@ -108,6 +108,15 @@ def forward(theta, x, d, lo, hi, bf16_emulation: bool = True):
     return V, U, dict(hs=hs, zs=zs, V=V, U=U)
 
 
+def head_abs_terms(theta, cache):
+    """[n, 2]: sum_k |W5[k, c] h4[k]| for each sample and head output c, the
+    magnitudes of the terms of the last product (bf16 operands). One BF16
+    rounding of a layer input that comes out differently moves an output by
+    about 2^-8 of such a sum; it is the error scale of the outputs."""
+    W5 = unpack(np.asarray(theta, np.float64))[-1][0]
+    return np.abs(cache["hs"][-1]) @ np.abs(bf16(W5))
+
+
 def loss_and_grad(theta, x, d, T, lo, hi, bf16_emulation: bool = True, e_fixed=None):
     """(mean loss, gradient [n_params]) of BCE(V, T) + |U - e| with e = |T - V|
     held constant (stop-gradient). e_fixed replaces e by given values, so that

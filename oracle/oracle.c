@@ -35,6 +35,7 @@
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no -ffast-math).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -688,3 +689,8 @@ void or_refit(int64_t n, const int32_t *left, const int32_t *right, const double
     free(st);
     free(seen);
 }
+
+/* Threads the parallel loops use, and a way to set them (the CPU baseline is
+ * timed on all host cores and on one). */
+int32_t or_max_threads(void) { return (int32_t)omp_get_max_threads(); }
+void or_set_threads(int32_t t) { omp_set_num_threads(t > 0 ? t : 1); }

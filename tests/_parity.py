@@ -24,7 +24,10 @@ def check_vis(v_gpu: np.ndarray, orc: dict, tol: float = TOL, label: str = "") -
     bad = ~((v >= lo) & (v <= hi))
     err = np.abs(v - orc["P"])
     clean = orc["n_amb"] == 0
-    stats = dict(rays=int(v.size), ambiguous_rays=int((~clean).sum()), fails=int(bad.sum()),
+    # ambiguous rays whose value is not the plain definition's: binary32 took
+    # the other decision on at least one pair within rounding of a cut
+    non_p = int(((~clean) & (err > tol)).sum())
+    stats = dict(rays=int(v.size), ambiguous_rays=int((~clean).sum()), ambiguous_non_p=non_p, fails=int(bad.sum()),
                  max_err_clean=float(err[clean].max()) if clean.any() else 0.0,
                  mean_err=float(err.mean()), max_err=float(err.max()))
     print(f"[parity {label}] {stats}", flush=True)

@@ -5,7 +5,8 @@
 2. Differentiation workload at full size (200,000 object-scale Gaussians x 128
    hemisphere directions): 64 seeded parameters against FP64 central finite
    differences of the oracle (h = 1e-4, plus a Richardson step), relative
-   error <= 1e-3 with the denominator max(|g_fd|, 1e-3 RMS over the 64).
+   error <= 1e-3 on every one of the 64, with the denominator
+   max(|g_fd|, 1e-3 RMS over the 64).
    T_min = 0 in both; a parameter is redrawn if any affected ray changes its
    included set, its clamp state or is ambiguous under binary32 rounding
    between theta - h and theta + h (the cuts make T piecewise smooth).
@@ -67,7 +68,9 @@ def test_adjoint_matches_oracle_analytic_small(use_fwd):
         diff = np.abs(got.astype(np.float64) - exp)
         # 1e-3 relative, widened by kappa = 8 times each element's first-order
         # sensitivity to binary32 rounding of the rays and of W (far-field
-        # near-misses of thin Gaussians: |p| ~ 1e3 whitened units)
+        # near-misses of thin Gaussians: |p| ~ 1e3 whitened units); that a
+        # binary32 evaluation stays within this bound is pinned on the CPU
+        # (test_oracle_adjoint_pins.py)
         tol = 1e-3 * np.maximum(np.abs(exp), 1e-3 * rms) + KAPPA_G * sens[name]
         err = _rel(got.astype(np.float64), exp, 1e-3 * rms)
         print(f"[adjoint small {name}] rms {rms:.3e} rel err max {err.max():.2e} p50 {np.median(err):.2e} "
@@ -259,16 +262,14 @@ def test_adjoint_fd_differentiation_workload_full_size():
     floor = 1e-3 * np.sqrt(np.mean(rich ** 2))
     err_rich = _rel(got, rich, floor)
     err_fd = _rel(got, fd, floor)
-    # relative error <= 1e-3 (denominator max(|g_fd|, 1e-3 RMS)); a parameter
-    # whose binary32 ray-rounding sensitivity exceeds that is held to kappa x it
+    # relative error <= 1e-3 on every one of the 64 (denominator
+    # max(|g_fd|, 1e-3 RMS)), the bar of the differentiation check
     ok_rel = err_rich <= 1e-3
-    ok_sens = np.abs(got - rich) <= KAPPA_G * sens
     print(f"[adjoint fd full] params {len(params)}, nonzero {(np.abs(rich) > floor).sum()}, rays/param "
           f"{np.mean([p['rays'] for p in params]):.0f}; rel err vs Richardson max {err_rich.max():.2e} "
           f"median {np.median(err_rich):.2e}; vs plain h=1e-4 max {err_fd.max():.2e} median {np.median(err_fd):.2e}; "
-          f"within 1e-3: {ok_rel.sum()}, within the binary32 bound only: {(~ok_rel & ok_sens).sum()}", flush=True)
-    for p, e, ok in zip(params, err_rich, ok_rel):
-        if not ok:
-            print(f"   {p['kind']}[{p['j']},{p['comp']}] rel {e:.2e} sens/|g| {p['sens'] / max(abs(p['rich']), 1e-30):.2e}")
-    assert np.all(ok_rel | ok_sens)
-    assert ok_rel.mean() >= 0.9
+          f"within 1e-3: {ok_rel.sum()}", flush=True)
+    for p, e in sorted(zip(params, err_rich), key=lambda t: -t[1])[:5]:
+        print(f"   {p['kind']}[{p['j']},{p['comp']}] rel {e:.2e} binary32 bound/|g| "
+              f"{KAPPA_G * p['sens'] / max(abs(p['rich']), 1e-30):.2e}", flush=True)
+    assert np.all(ok_rel)

@@ -66,8 +66,10 @@ def test_trace_beyond_2_32_lane_rays():
 
 def test_surrogate_scale_full_size_sampled():
     """3M Gaussians (20 objects) x 1,024 hemisphere directions, traced as the
-    bench traces it; 96 seeded rays against the brute-force FP64 oracle, and
-    the means of 8 Gaussians against their 1,024 rays."""
+    bench traces it (the all-ray kernel writing all 3.07e9 rays); 16,384 seeded
+    rays of that output against the brute-force FP64 oracle, the ray-list
+    kernel giving them the same bits, and the means of 8 Gaussians against
+    their 1,024 rays."""
     sc = scenes.make_scene("surrogate")
     dirs = scenes.preset_dirs("surrogate")
     n, K = sc["mean"].shape[0], dirs.shape[0]
@@ -75,15 +77,21 @@ def test_surrogate_scale_full_size_sampled():
     prm = TraceParams()
     g = Gaussians.from_scene(sc)
     bvh = build_bvh(g)
-    _, vm = trace_visibility(bvh, g, dirs, prm, want_ray=False)
-    ids = scenes.sample_ray_ids(n, K, 96, seed=17)
-    vr = trace_rays(bvh, g, dirs, ids, prm).cpu().numpy()
+    vr_all, vm = trace_visibility(bvh, g, dirs, prm)
+    ids = scenes.sample_ray_ids(n, K, 16384, seed=17)
+    sample = np.random.default_rng(18).integers(0, n, 8)
+    rows = (sample[:, None] * K + np.arange(K)[None, :]).reshape(-1)
+    flat = vr_all.reshape(-1)
+    vr = flat[torch.from_numpy(ids).cuda()].cpu().numpy()
+    row_vals = flat[torch.from_numpy(rows).cuda()].cpu().numpy()
+    del vr_all, flat
+    lst = trace_rays(bvh, g, dirs, ids, prm).cpu().numpy()
+    assert np.array_equal(lst.view(np.uint32), vr.view(np.uint32))
+    print(f"[large] oracle on {ids.size} rays", flush=True)
     orc = oracle.trace_rays(sc, dirs, 1, ids, oracle.params(alpha_min=1 / 255, alpha_max=0.99,
                                                             sigma_cut=prm.sigma_cut, tmin_scale=prm.tmin_scale))
     check_vis(vr, orc, label="surrogate-scale sampled")
-    sample = np.random.default_rng(18).integers(0, n, 8)
-    rows = (sample[:, None] * K + np.arange(K)[None, :]).reshape(-1)
-    T = trace_rays(bvh, g, dirs, rows, prm).cpu().numpy().astype(np.float64).reshape(-1, K)
+    T = row_vals.astype(np.float64).reshape(-1, K)
     want = (T.sum(1) / K).astype(np.float32)
     got = vm.cpu().numpy()[sample]
     assert np.all(np.abs(got - want) <= 2 * np.spacing(np.abs(want))), np.abs(got - want).max()

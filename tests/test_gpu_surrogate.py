@@ -1,6 +1,13 @@
-"""MLP surrogate on the matrix cores vs the FP64 oracle with bfloat16 emulation
-(relative Frobenius error <= 1e-2), grid inference with tracer fallback, and
-what training on tracer samples gains over the untrained network."""
+"""MLP surrogate on the matrix cores vs the FP64 oracle with bfloat16 emulation,
+grid inference with tracer fallback, and what training on tracer samples gains
+over the untrained network.
+
+Bounds (their derivation and a CPU pin against a binary32/BF16 evaluation are
+in test_oracle_mlp_pins.py): each output V, U within 2^-8 of the magnitude sum
+of the last product's terms (V through the sigmoid's slope <= 1/4), and the
+outputs' relative Frobenius error <= 1e-3; per layer, the gradient's relative
+Frobenius error <= 4e-3 and its largest element error <= 1e-2 of its largest
+element."""
 import numpy as np
 import pytest
 import torch
@@ -8,6 +15,8 @@ import torch
 from oracle import mlp
 from paper_2311_16043_amd import Gaussians, Surrogate, TraceParams, build_bvh, ray_setup, trace_rays, trace_visibility
 from workloads import mlp_init, scenes
+
+from test_oracle_mlp_pins import C_OUT, GRAD_FROB, GRAD_MAXABS, OUT_FROB, layer_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -38,11 +47,18 @@ def test_forward_matches_oracle(n):
     x, d, _ = _inputs(n, 1)
     vis, unc = net.infer_xd(torch.from_numpy(x), torch.from_numpy(d))
     torch.cuda.synchronize()
-    V, U, _ = mlp.forward(w, x, d, BOX_LO.astype(np.float32), BOX_HI.astype(np.float32))
-    ev, eu = _relf(vis.cpu().numpy(), V), _relf(unc.cpu().numpy(), U)
-    print(f"[surrogate fwd n={n}] rel Frobenius V {ev:.2e} U {eu:.2e}; max |dV| "
-          f"{np.abs(vis.cpu().numpy() - V).max():.2e}", flush=True)
-    assert ev <= 1e-2 and eu <= 1e-2
+    V, U, cache = mlp.forward(w, x, d, BOX_LO.astype(np.float32), BOX_HI.astype(np.float32))
+    A = mlp.head_abs_terms(w, cache)
+    v, u = vis.cpu().numpy().astype(np.float64), unc.cpu().numpy().astype(np.float64)
+    ev, eu = _relf(v, V), _relf(u, U)
+    # each output on its own: V = sigmoid(z0) (slope <= 1/4), U = softplus(z1)
+    # (slope <= 1), plus the binary32 rounding of those functions
+    rv = np.abs(v - V) / (0.25 * C_OUT * 2.0 ** -8 * A[:, 0] + 2.0 ** -22)
+    ru = np.abs(u - U) / (C_OUT * 2.0 ** -8 * A[:, 1] + 2.0 ** -22 * np.maximum(U, 1.0))
+    print(f"[surrogate fwd n={n}] rel Frobenius V {ev:.2e} U {eu:.2e}; max |dV| {np.abs(v - V).max():.2e}; "
+          f"max error / element bound V {rv.max():.3f} U {ru.max():.3f}", flush=True)
+    assert ev <= OUT_FROB and eu <= OUT_FROB
+    assert np.all(rv <= 1.0) and np.all(ru <= 1.0)
     # the master copy holds the uploaded weights exactly
     assert np.array_equal(net.master.cpu().numpy(), w)
 
@@ -56,13 +72,9 @@ def test_loss_and_gradient_match_oracle(n):
     lref, gref = mlp.loss_and_grad(w, x, d, T, BOX_LO.astype(np.float32), BOX_HI.astype(np.float32))
     g = grad.cpu().numpy()
     assert abs(float(loss) - lref) <= 1e-3 * abs(lref)
-    o = 0
-    for li, (a, b) in enumerate(mlp.SHAPES):
-        for name, size in (("W", a * b), ("b", b)):
-            e = _relf(g[o:o + size], gref[o:o + size])
-            print(f"[surrogate grad n={n}] layer {li + 1} {name}: rel Frobenius {e:.2e}", flush=True)
-            assert e <= 1e-2, (li, name, e)
-            o += size
+    for name, f, m in layer_errors(g, gref):
+        print(f"[surrogate grad n={n}] {name}: rel Frobenius {f:.2e}, max |dg| / max |g| {m:.2e}", flush=True)
+        assert f <= GRAD_FROB and m <= GRAD_MAXABS, (name, f, m)
     # deterministic
     _, grad2 = net.loss_grad(torch.from_numpy(x), torch.from_numpy(d), torch.from_numpy(T))
     assert torch.equal(grad, grad2)
@@ -94,7 +106,8 @@ def test_adam_step_matches_oracle():
     print(f"[surrogate adam] rel Frobenius m {em:.2e} v {ev:.2e}; own-update max dev {eo:.2e} lr; "
           f"{off.mean():.2e} of weights off by > 0.1 lr, max |g|/RMS among them "
           f"{(np.abs(g[off]).max() / rms) if off.any() else 0:.2e}", flush=True)
-    assert em <= 1e-2 and ev <= 1e-2
+    # m is linear in the gradient (its per-layer bound), v quadratic (twice it)
+    assert em <= GRAD_FROB and ev <= 2 * GRAD_FROB
     assert eo <= 1e-3
     assert not off.any() or np.abs(g[off]).max() <= 0.1 * rms
 
@@ -125,12 +138,33 @@ def test_grid_inference_with_fallback_matches_tracer():
     assert np.array_equal(vx.cpu().numpy().view(np.uint32), vis0.cpu().numpy()[:4096].view(np.uint32))
 
 
+def _fallback_tau(u, err, target):
+    """Smallest fallback set (queries with the largest predicted error U are
+    traced exactly) whose mean error over all queries stays <= target:
+    (tau, fallback fraction, MAE)."""
+    order = torch.argsort(u, descending=True)
+    e = err[order]
+    kept = torch.flip(torch.cumsum(torch.flip(e, [0]), 0), [0]) / err.numel()   # MAE if the first j are traced
+    ok = torch.nonzero(kept <= target)
+    j = int(ok[0]) if ok.numel() else err.numel()
+    tau = float(u[order[j]]) if j < err.numel() else float("-inf")
+    return tau, j / err.numel(), float(kept[j]) if j < err.numel() else 0.0
+
+
+def _with_fallback(u, err, tau):
+    fb = u > tau
+    return float(fb.float().mean()), float(torch.where(fb, torch.zeros_like(err), err).mean())
+
+
 def test_training_on_tracer_samples_beats_untrained_network():
-    """Train on the tracer's own visibility: on held-out queries the trained
-    network's error is far below the untrained one's, and its predicted error
-    ranks the queries: the 20 % it flags for fallback carry well above the
-    mean error of the rest, so tracing them lowers the combined error more
-    than tracing a random 20 % would."""
+    """Train on the tracer's own visibility, pick the fallback threshold tau on
+    held-out queries for a mean error <= 0.02, and check on separate test
+    queries: the trained network meets the target there while tracing only
+    part of the queries; its predicted error ranks the queries (correlation
+    with the actual error, and the flagged queries carry well above the mean
+    error of the rest); the untrained network at the same tau either traces
+    nearly everything or misses the target, and at the trained network's
+    fallback fraction its error is several times the target."""
     sc = scenes.make_object_scene(50_000, 1)
     K = 64
     dirs = scenes.fibonacci_dirs(K, True)
@@ -140,28 +174,42 @@ def test_training_on_tracer_samples_beats_untrained_network():
     T_all = vr.reshape(-1)
     rng = np.random.default_rng(9)
     perm = rng.permutation(50_000 * K)
-    train_ids, test_ids = perm[:2_000_000], perm[-200_000:]
+    train_ids, held_ids, test_ids = perm[:2_000_000], perm[-400_000:-200_000], perm[-200_000:]
     o, d = ray_setup(g, dirs, train_ids)
     net = Surrogate(sc["mean"].min(0), sc["mean"].max(0), seed=3)
+    untrained = Surrogate(sc["mean"].min(0), sc["mean"].max(0), seed=3)
+    oh, dh = ray_setup(g, dirs, held_ids)
     ot, dt = ray_setup(g, dirs, test_ids)
-    v0, _ = net.infer_xd(ot, dt)
+    Th = T_all[torch.from_numpy(held_ids).cuda()]
     Tt = T_all[torch.from_numpy(test_ids).cuda()]
-    mae0 = float((v0 - Tt).abs().mean())
     log = net.train(o, d, T_all[torch.from_numpy(train_ids).cuda()], steps=600, batch=8192, lr=2e-3, lr_min=1e-4,
                     seed=1)
-    v1, u1 = net.infer_xd(ot, dt)
-    err = (v1 - Tt).abs()
-    mae1 = float(err.mean())
-    # fallback: queries with the largest predicted error are traced exactly
-    tau = float(torch.quantile(u1, 0.8))
-    fb = u1 > tau
-    mae_fb = float(torch.where(fb, torch.zeros_like(err), err).mean())
-    corr = float(torch.corrcoef(torch.stack([u1, err]))[0, 1])
-    print(f"[surrogate train] loss {float(log[0]):.4f} -> {float(log[-1]):.4f}; MAE untrained {mae0:.4f}, "
-          f"trained {mae1:.4f}, with {float(fb.float().mean()):.0%} fallback {mae_fb:.4f}; "
-          f"corr(U, |err|) {corr:.2f}", flush=True)
-    ratio = float(err[fb].mean() / err[~fb].mean())
-    print(f"[surrogate train] mean |err| flagged / rest = {ratio:.2f}", flush=True)
+    target = 0.02
+    res = {}
+    for name, m in (("trained", net), ("untrained", untrained)):
+        vh, uh = m.infer_xd(oh, dh)
+        tau, f_held, _ = _fallback_tau(uh, (vh - Th).abs(), 0.95 * target)
+        vt, ut = m.infer_xd(ot, dt)
+        err = (vt - Tt).abs()
+        f, mae_fb = _with_fallback(ut, err, tau)
+        corr = float(torch.corrcoef(torch.stack([ut, err]))[0, 1])
+        res[name] = dict(tau=tau, f=f, mae=float(err.mean()), mae_fb=mae_fb, corr=corr, u=ut, err=err)
+        print(f"[surrogate gain] {name}: MAE {res[name]['mae']:.4f}; tau {tau:.4g} traces {f:.1%} of the test "
+              f"queries, MAE with fallback {mae_fb:.4f}; corr(U, |err|) {corr:.2f}", flush=True)
+    tr, un = res["trained"], res["untrained"]
+    # the untrained network at the trained network's tau, and at its fallback fraction
+    f_same, mae_same = _with_fallback(un["u"], un["err"], tr["tau"])
+    k = int(tr["f"] * un["err"].numel())
+    order = torch.argsort(un["u"], descending=True)
+    mae_same_f = float(un["err"][order[k:]].sum() / un["err"].numel())
+    flagged = tr["u"] > tr["tau"]
+    ratio = float(tr["err"][flagged].mean() / tr["err"][~flagged].mean()) if flagged.any() else float("inf")
+    print(f"[surrogate gain] loss {float(log[0]):.4f} -> {float(log[-1]):.4f}; untrained at the trained tau: traces "
+          f"{f_same:.1%}, MAE {mae_same:.4f}; untrained tracing the trained fraction {tr['f']:.1%}: MAE "
+          f"{mae_same_f:.4f}; trained flagged/rest mean error {ratio:.2f}", flush=True)
     assert float(log[-1]) < float(log[0])
-    assert mae1 < 0.5 * mae0
-    assert ratio > 1.2 and mae_fb < 0.8 * mae1
+    assert tr["mae"] < 0.5 * un["mae"]
+    assert tr["mae_fb"] <= target and tr["f"] < 0.8
+    assert ratio > 1.5 and tr["corr"] > 0.1
+    assert f_same > 0.95 or mae_same > target
+    assert mae_same_f > 2 * target

@@ -1,0 +1,209 @@
+"""Pins of the oracle's per-pair terms and of its binary32 error scale.
+
+1. `or_pair_terms` (one Gaussian against many rays; it builds the finite
+   differences of the differentiation check) against `or_trace_rays` (every
+   Gaussian against one ray, pinned by closed forms in test_oracle_pins.py):
+   per ray, the product of (1 - min(alpha, 0.99)) over the pairs it marks
+   included equals the brute-force P (the Eq. (15) product), its included,
+   clamped and ambiguous counts equal the ray's, its pairs span the ray's
+   acceptance band, and its t* and q equal `or_peak` (pinned by a dense search).
+2. `or_grad_rays(absolute=2)`, the first-order sensitivity of each adjoint
+   term to binary32 rounding of the ray and of W, bounds what a binary32
+   evaluation of the adjoint actually deviates: every step of the per-hit
+   arithmetic (ray setup, whitening rows with row 2 rebuilt as a scaled cross
+   product, p, v, t*, q, alpha, e = p + t* v, W^T e, the seven terms) is
+   evaluated in numpy float32, the terms are summed in FP64 (so only the
+   per-term rounding is measured), and the deviation from the FP64 analytic
+   gradient must stay within KAPPA_G times the bound on every element.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import scenes
+
+KAPPA_G = 8.0  # the factor the GPU adjoint tests apply to the bound
+
+
+def _scene(n, K, seed):
+    sc = scenes.make_object_scene(n, seed)
+    return sc, scenes.fibonacci_dirs(K, True)
+
+
+def _dense_scene(n, seed):
+    """A cube cloud shrunk into [-0.25, 0.25]^3 with opacities up to 1: many
+    overlaps per ray, clamped pairs, and rays that end near zero."""
+    sc = scenes.make_cube_cloud(n, seed)
+    sc["mean"] = (sc["mean"] * np.float32(0.25)).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    op = rng.uniform(0.05, 1.0, n)
+    hot = rng.random(n) < 0.2
+    op[hot] = rng.uniform(0.992, 1.0, hot.sum())   # alpha reaches the 0.99 clamp near the peak
+    sc["opacity"] = op.astype(np.float32)
+    return sc
+
+
+def test_pair_terms_agree_with_brute_force_rays():
+    n, K = 300, 8
+    sc, dirs = _dense_scene(n, 5), scenes.fibonacci_dirs(K, True)
+    rays = np.arange(n * K, dtype=np.int64)
+    orc = oracle.trace_rays(sc, dirs, 1, rays)
+    amax = oracle.ALPHA_MAX
+    prod = np.ones(n * K)
+    lo, hi = np.ones(n * K), np.ones(n * K)
+    inc_n = np.zeros(n * K, np.int64)
+    amb_n = np.zeros(n * K, np.int64)
+    clamp_n = np.zeros(n * K, np.int64)
+    src = rays // K
+    for j in range(n):
+        t = oracle.pair_terms(sc, dirs, 1, rays, j)
+        inc, amb = t["inc"] > 0, t["amb"] > 0
+        f = 1.0 - np.minimum(t["alpha"], amax)
+        prod *= np.where(inc, f, 1.0)
+        lo *= np.where(inc | amb, f, 1.0)      # every possibly included pair
+        hi *= np.where(inc & ~amb, f, 1.0)     # the surely included pairs
+        inc_n += inc
+        amb_n += amb
+        clamp_n += inc & (t["alpha"] >= amax)
+        # a Gaussian never occludes its own rays
+        assert not inc[src == j].any() and not amb[src == j].any()
+        if j % 50 == 0:
+            for s in (0, 777, 1999):
+                o, d, _ = oracle.make_ray(sc, dirs, 1, int(rays[s]))
+                tp, qp = oracle.peak(sc["quat"][j], sc["log_scale"][j], sc["mean"][j], o, d)
+                assert t["t"][s] == pytest.approx(tp, rel=1e-12, abs=1e-12)
+                assert t["q"][s] == pytest.approx(qp, rel=1e-12, abs=1e-12)
+                assert t["alpha"][s] == pytest.approx(float(sc["opacity"][j]) * np.exp(-0.5 * qp), rel=1e-12)
+    assert np.allclose(prod, orc["P"], rtol=1e-12, atol=0)
+    assert np.allclose(lo, orc["V_lo"], rtol=1e-12, atol=0)
+    assert np.allclose(hi, orc["V_hi"], rtol=1e-12, atol=0)
+    assert np.array_equal(inc_n, orc["n_incl"])
+    assert np.array_equal(amb_n, orc["n_amb"])
+    assert np.array_equal(clamp_n, orc["n_clamp"])
+    print(f"[pair terms] {inc_n.sum()} included pairs, {clamp_n.sum()} clamped, {amb_n.sum()} ambiguous; "
+          f"rays with P < 0.5: {(orc['P'] < 0.5).sum()}", flush=True)
+    assert inc_n.sum() > 5000 and clamp_n.sum() >= 5 and (orc["P"] < 0.5).sum() > 500
+
+
+def _f32(x):
+    return np.asarray(x, np.float32)
+
+
+def _rays_f32(sc, dirs, rays, K):
+    """Origins, directions and t_min of rays r = i K + k in binary32, as the
+    tracer forms them: the normal normalised, the Duff et al. 2017 basis, the
+    rotated direction normalised by its reciprocal square root."""
+    i = rays // K
+    k = rays % K
+    o = _f32(sc["mean"][i])
+    nr = _f32(sc["normal"][i])
+    nr = nr / np.sqrt(np.sum(nr * nr, 1, keepdims=True, dtype=np.float32))
+    sign = np.copysign(np.float32(1), nr[:, 2]).astype(np.float32)
+    a = (np.float32(-1) / (sign + nr[:, 2])).astype(np.float32)
+    b = nr[:, 0] * nr[:, 1] * a
+    b1 = np.stack([np.float32(1) + sign * nr[:, 0] * nr[:, 0] * a, sign * b, -sign * nr[:, 0]], 1)
+    b2 = np.stack([b, sign + nr[:, 1] * nr[:, 1] * a, -nr[:, 1]], 1)
+    dk = _f32(dirs)[k]
+    d = dk[:, 0:1] * b1 + dk[:, 1:2] * b2 + dk[:, 2:3] * nr
+    d = d * (np.float32(1) / np.sqrt(np.sum(d * d, 1, keepdims=True, dtype=np.float32)))
+    smax = np.exp(_f32(sc["log_scale"][i]).max(1))
+    return o.astype(np.float32), d.astype(np.float32), (np.float32(3) * smax).astype(np.float32)
+
+
+def _whitening_f32(sc, j):
+    """Rows 0 and 1 of W = diag(1/s) R^T in binary32 and row 2 rebuilt as
+    (s0 s1 / s2)(row 0 x row 1), as the leaf records hold them."""
+    q = _f32(sc["quat"][j])
+    q = q / np.sqrt(np.sum(q * q, 1, keepdims=True, dtype=np.float32))
+    w, x, y, z = (q[:, c] for c in range(4))
+    one, two = np.float32(1), np.float32(2)
+    R = np.empty((j.size, 3, 3), np.float32)
+    R[:, 0, 0] = one - two * (y * y + z * z); R[:, 0, 1] = two * (x * y - w * z); R[:, 0, 2] = two * (x * z + w * y)
+    R[:, 1, 0] = two * (x * y + w * z); R[:, 1, 1] = one - two * (x * x + z * z); R[:, 1, 2] = two * (y * z - w * x)
+    R[:, 2, 0] = two * (x * z - w * y); R[:, 2, 1] = two * (y * z + w * x); R[:, 2, 2] = one - two * (x * x + y * y)
+    ls = _f32(sc["log_scale"][j])
+    s, inv = np.exp(ls), np.exp(-ls)
+    w0 = inv[:, 0:1] * R[:, :, 0]
+    w1 = inv[:, 1:2] * R[:, :, 1]
+    c = s[:, 0] * s[:, 1] * inv[:, 2]
+    w2 = c[:, None] * np.cross(w0, w1).astype(np.float32)
+    return w0.astype(np.float32), w1.astype(np.float32), w2.astype(np.float32)
+
+
+def _dot(a, b):
+    return (a[:, 0] * b[:, 0] + a[:, 1] * b[:, 1] + a[:, 2] * b[:, 2]).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind,n,K", [("object", 4000, 16), ("dense", 600, 16)])
+def test_binary32_adjoint_deviation_within_the_sensitivity_bound(kind, n, K):
+    if kind == "object":   # thin surface Gaussians: far-field near-misses, |p| ~ 1e3
+        sc, dirs = _scene(n, K, 3)
+    else:                  # a dense cluster: long products, small T_final
+        sc, dirs = _dense_scene(n, 7), scenes.fibonacci_dirs(K, True)
+    rays = np.arange(n * K, dtype=np.int64)
+    orc = oracle.trace_rays(sc, dirs, 1, rays)
+    w = np.random.default_rng(42).uniform(-1.0, 1.0, n * K)
+    # rays on which binary32 may take another decision carry no gradient,
+    # exactly as in the GPU adjoint tests
+    w[(orc["n_amb"] > 0) | (orc["n_near_clamp"] > 0)] = 0.0
+    ref = oracle.grad_rays(sc, dirs, 1, rays, w)
+    sens = oracle.grad_rays(sc, dirs, 1, rays, w, absolute=2)
+
+    # the included pairs, from the (pinned) per-pair oracle
+    pr, pj = [], []
+    for j in range(n):
+        t = oracle.pair_terms(sc, dirs, 1, rays, j)
+        sel = np.nonzero(t["inc"] > 0)[0]
+        pr.append(sel)
+        pj.append(np.full(sel.size, j, np.int64))
+    pr, pj = np.concatenate(pr), np.concatenate(pj)
+    live = w[pr] != 0.0
+    pr, pj = pr[live], pj[live]
+    assert pr.size > 10_000
+
+    # binary32 evaluation of each included pair
+    o, d, _ = _rays_f32(sc, dirs, rays[pr], K)
+    w0, w1, w2 = _whitening_f32(sc, pj)
+    x = (o - _f32(sc["mean"][pj])).astype(np.float32)
+    p = np.stack([_dot(w0, x), _dot(w1, x), _dot(w2, x)], 1)
+    v = np.stack([_dot(w0, d), _dot(w1, d), _dot(w2, d)], 1)
+    vv, pv = _dot(v, v), _dot(p, v)
+    cp = np.cross(p, v).astype(np.float32)
+    q = (_dot(cp, cp) / vv).astype(np.float32)
+    op = _f32(sc["opacity"][pj])
+    alpha = (op * np.exp(np.float32(-0.5) * q)).astype(np.float32)
+    clamped = alpha >= np.float32(oracle.ALPHA_MAX)
+    one_minus = np.where(clamped, np.float32(1 - oracle.ALPHA_MAX), np.float32(1) - alpha).astype(np.float32)
+    tstar = (-pv / vv).astype(np.float32)
+    e = (p + tstar[:, None] * v).astype(np.float32)
+    wte = (e[:, 0:1] * w0 + e[:, 1:2] * w1 + e[:, 2:3] * w2).astype(np.float32)
+    # T_final of each ray in binary32 (product over its included pairs)
+    logT = np.zeros(n * K)
+    np.add.at(logT, pr, np.log(one_minus.astype(np.float64)))
+    T = np.exp(logT).astype(np.float32)
+    g_over = (-_f32(w[pr]) * T[pr]).astype(np.float32)
+    a = (g_over / one_minus * alpha).astype(np.float32)
+    a = np.where(clamped, np.float32(0), a)
+
+    go, gm, gl = np.zeros(n), np.zeros((n, 3)), np.zeros((n, 3))
+    np.add.at(go, pj, (a / op).astype(np.float64))
+    np.add.at(gm, pj, (a[:, None] * wte).astype(np.float64))
+    np.add.at(gm, pr // K, -(a[:, None] * wte).astype(np.float64))
+    np.add.at(gl, pj, (a[:, None] * e * e).astype(np.float64))
+
+    worst = {}
+    for name, got in (("opacity", go), ("mean", gm), ("log_scale", gl)):
+        dev = np.abs(got - ref[name])
+        bound = KAPPA_G * sens[name]
+        rms = float(np.sqrt(np.mean(ref[name] ** 2)))
+        # the FP64 evaluation itself is exact to ~1e-15 relative
+        ok = dev <= bound + 1e-12 * rms
+        ratio = dev / np.maximum(sens[name], 1e-300)
+        worst[name] = float(ratio[sens[name] > 0].max())
+        rel = dev / np.maximum(np.abs(ref[name]), 1e-3 * rms)
+        print(f"[binary32 adjoint {name}] max dev/sens {worst[name]:.3f}, max rel dev {rel.max():.2e}, "
+              f"elements beyond 1e-3 relative {(rel > 1e-3).sum()}", flush=True)
+        assert np.all(ok), (name, float((dev / np.maximum(bound, 1e-300)).max()))
+    # the bound is an error scale, not a loose ceiling: the measured deviation
+    # reaches a visible fraction of it on some element
+    assert max(worst.values()) > 0.01

@@ -103,3 +103,87 @@ def test_forward_ranges_and_init_shapes():
     x, d, T = _data(100, 4)
     V, U, _ = mlp.forward(theta, x, d, -2 * np.ones(3), 2 * np.ones(3))
     assert np.all((V > 0) & (V < 1)) and np.all(U >= 0)
+
+
+# Error scales of a BF16/FP32 evaluation: the network run with binary32
+# accumulation (numpy float32 products and sums) and BF16 rounding of every
+# product operand at the points the oracle rounds, against the FP64 oracle.
+# The GPU parity tests apply the same bounds with the same constants.
+# Outputs: one BF16 rounding of a layer input that comes out differently
+# moves an output by about 2^-8 of the magnitude sum of the last product's
+# terms, so each output is checked on its own. Gradients: a hidden
+# pre-activation within rounding of zero switches its ReLU and adds or drops
+# a whole term (94 % of samples have a unit within 2^-11 of its terms'
+# magnitude sum of zero), so element bounds are either unsound or far above
+# the gradient itself; each layer is checked by its relative Frobenius error
+# and its largest element error relative to its largest element (one element
+# off by a typical magnitude in a 64 x 256 layer moves the first to ~8e-3).
+C_OUT = 1.0          # outputs: |dz_c| <= C_OUT 2^-8 sum_k |W5[k, c] h4[k]|
+OUT_FROB = 1e-3      # relative Frobenius error of V and U
+GRAD_FROB = 4e-3     # per-layer relative Frobenius error of W and b gradients
+GRAD_MAXABS = 1e-2   # per-layer max |dg| / max |g|
+
+
+def _f32_network(theta, x, d, T, lo, hi):
+    """(z5 [n, 2], flat gradient) in binary32 with BF16 product operands."""
+    bf = lambda a: mlp.bf16(a).astype(np.float32)
+    layers = mlp.unpack(np.asarray(theta, np.float64))
+    h = mlp.encode(mlp.normalize(x, lo, hi), d).astype(np.float32)
+    hs, zs = [], []
+    for li, (W, b) in enumerate(layers):
+        hin = bf(h)
+        hs.append(hin)
+        z = (hin @ bf(W) + b.astype(np.float32)).astype(np.float32)
+        zs.append(z)
+        h = np.maximum(z, np.float32(0)) if li < len(layers) - 1 else z
+    z5 = zs[-1]
+    n = x.shape[0]
+    V = (1 / (1 + np.exp(-z5[:, 0]))).astype(np.float32)
+    U = (np.maximum(z5[:, 1], 0) + np.log1p(np.exp(-np.abs(z5[:, 1])))).astype(np.float32)
+    e = np.abs(T.astype(np.float32) - V)
+    dz = np.zeros((n, 2), np.float32)
+    dz[:, 0] = (V - T) / np.float32(n)
+    dz[:, 1] = np.sign(U - e) / (1 + np.exp(-z5[:, 1])) / np.float32(n)
+    grads = [None] * len(layers)
+    for li in range(len(layers) - 1, -1, -1):
+        dzr = bf(dz)
+        grads[li] = ((hs[li].T @ dzr).astype(np.float32), dz.sum(0, dtype=np.float32))
+        if li > 0:
+            dz = ((dzr @ bf(layers[li][0]).T) * (zs[li - 1] > 0)).astype(np.float32)
+    return z5, np.concatenate([np.concatenate([a.reshape(-1), b]) for a, b in grads])
+
+
+def layer_errors(got, ref):
+    """[(name, relative Frobenius error, max |error| / max |ref|)] per W and b."""
+    out, o = [], 0
+    for li, (a, b) in enumerate(mlp.SHAPES):
+        for name, size in (("W", a * b), ("b", b)):
+            g, r = np.asarray(got[o:o + size], np.float64), ref[o:o + size]
+            out.append((f"{name}{li + 1}", float(np.linalg.norm(g - r) / np.linalg.norm(r)),
+                        float(np.abs(g - r).max() / np.abs(r).max())))
+            o += size
+    return out
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5, 6])
+def test_binary32_network_within_the_output_and_gradient_bounds(seed):
+    x, d, T = _data(2048, seed)
+    theta = mlp_init.he_uniform(10 + seed)
+    lo, hi = np.float32([-2, -2, -0.1]), np.float32([2, 2, 2.1])
+    V, U, cache = mlp.forward(theta, x, d, lo, hi)
+    A = mlp.head_abs_terms(theta, cache)
+    _, g = mlp.loss_and_grad(theta, x, d, T, lo, hi)
+    z5, g32 = _f32_network(theta, x, d, T, lo, hi)
+    dz = np.abs(z5.astype(np.float64) - cache["zs"][-1])
+    r_out = dz / (C_OUT * 2.0 ** -8 * A)
+    V32 = 1 / (1 + np.exp(-z5[:, 0].astype(np.float64)))
+    fv = np.linalg.norm(V32 - V) / np.linalg.norm(V)
+    errs = layer_errors(g32, g)
+    print(f"[bf16 bounds seed {seed}] outputs max |dz|/bound {r_out.max():.3f} (samples with any deviation "
+          f"{(dz.max(1) > 1e-6 * A.max(1)).mean():.3f}), V Frobenius {fv:.1e}; gradients worst Frobenius "
+          f"{max(e[1] for e in errs):.1e}, worst max-abs {max(e[2] for e in errs):.1e}", flush=True)
+    assert np.all(r_out <= 1.0) and fv <= OUT_FROB
+    assert all(f <= GRAD_FROB and m <= GRAD_MAXABS for _, f, m in errs), errs
+    # the output bound is of the right size: the largest deviations reach a
+    # visible fraction of it
+    assert r_out.max() > 0.01
