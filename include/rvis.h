@@ -314,12 +314,13 @@ rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaussians *g, c
  * as [u, sin(2^l pi u), cos(2^l pi u)] for l = 0, 1, 2 (42 features,
  * zero-padded to 64); four hidden layers of 256 with ReLU (64->256, then
  * 3 x 256->256); a 256->2 head giving V = sigmoid(z0) and the predicted
- * absolute error U = softplus(z1). Matrix products run on the gfx950 matrix
+ * absolute error U = z1 (linear). Matrix products run on the gfx950 matrix
  * cores in BF16 (weights and layer inputs rounded to nearest even) with FP32
  * accumulation; biases, nonlinearities, the loss, the master weights and Adam
  * are FP32.
- * Loss per sample: BCE(V, T) + |U - |T - V|| with V held constant in the
- * second term. Parameters: one flat FP32 vector W1, b1, ..., W5, b5, each W
+ * Loss per sample: BCE(V, T) + (U - |T - V|)^2 with V held constant in the
+ * second term, so that U estimates the mean absolute error of V given the
+ * query, by which the fallback ranks queries. Parameters: one flat FP32 vector W1, b1, ..., W5, b5, each W
  * stored [in][out] row-major (rv_surrogate_n_params() = 214,530 floats).
  */
 typedef struct rv_train_opts {

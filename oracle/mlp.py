@@ -7,9 +7,13 @@ visibility term V of Eq. (9)):
   encode  each scalar u -> [u, sin(2^l pi u), cos(2^l pi u)], l = 0, 1, 2;
           42 features, zero-padded to 64
   hidden  4 layers of 256 with ReLU (64->256, then 3 x 256->256)
-  head    256 -> 2: V = sigmoid(z0), U = softplus(z1) (predicted |T - V|)
-  loss    mean over the batch of BCE(V, T) + |U - |T - V||, V held constant
-          in the second term (no gradient flows from it into z0)
+  head    256 -> 2: V = sigmoid(z0), U = z1 (predicted |T - V|)
+  loss    mean over the batch of BCE(V, T) + (U - |T - V|)^2, V held constant
+          in the second term (no gradient flows from it into z0); the squared
+          error makes U the conditional mean of |T - V|, the quantity whose
+          largest values the tracer fallback should take. U is linear in z1:
+          a saturating activation (softplus) let the head collapse to ~0
+          where its gradient vanished, in short training runs
   Adam    Kingma & Ba (2015) with bias correction, cosine-decayed step size
 
 Parameters are one flat FP64 vector in the order W1, b1, ..., W5, b5 with
@@ -86,10 +90,6 @@ def _sigmoid(z):
     return 1.0 / (1.0 + np.exp(-z))
 
 
-def _softplus(z):
-    return np.maximum(z, 0.0) + np.log1p(np.exp(-np.abs(z)))
-
-
 def forward(theta, x, d, lo, hi, bf16_emulation: bool = True):
     """(V [n], U [n], cache) for inputs x [n, 3], d [n, 3]."""
     r = bf16 if bf16_emulation else (lambda a: np.asarray(a, np.float64))
@@ -104,7 +104,7 @@ def forward(theta, x, d, lo, hi, bf16_emulation: bool = True):
         h = np.maximum(z, 0.0) if li < len(layers) - 1 else z
     z = zs[-1]
     V = _sigmoid(z[:, 0])
-    U = _softplus(z[:, 1])
+    U = z[:, 1].copy()
     return V, U, dict(hs=hs, zs=zs, V=V, U=U)
 
 
@@ -118,7 +118,7 @@ def head_abs_terms(theta, cache):
 
 
 def loss_and_grad(theta, x, d, T, lo, hi, bf16_emulation: bool = True, e_fixed=None):
-    """(mean loss, gradient [n_params]) of BCE(V, T) + |U - e| with e = |T - V|
+    """(mean loss, gradient [n_params]) of BCE(V, T) + (U - e)^2 with e = |T - V|
     held constant (stop-gradient). e_fixed replaces e by given values, so that
     finite differences of the returned loss see exactly the objective whose
     gradient is returned."""
@@ -130,11 +130,11 @@ def loss_and_grad(theta, x, d, T, lo, hi, bf16_emulation: bool = True, e_fixed=N
     eps = 1e-12
     e = np.abs(T - V) if e_fixed is None else np.asarray(e_fixed, np.float64)
     bce = -(T * np.log(np.maximum(V, eps)) + (1 - T) * np.log(np.maximum(1 - V, eps)))
-    loss = float(np.mean(bce + np.abs(U - e)))
+    loss = float(np.mean(bce + (U - e) ** 2))
     z5 = c["zs"][-1]
     dz = np.zeros((n, N_OUT))
     dz[:, 0] = (V - T) / n
-    dz[:, 1] = np.sign(U - e) * _sigmoid(z5[:, 1]) / n
+    dz[:, 1] = 2.0 * (U - e) / n
     layers = unpack(theta)
     grads = [None] * len(layers)
     for li in range(len(layers) - 1, -1, -1):

@@ -293,7 +293,7 @@ __device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
         const bool valid = s < a.n;
         const float z0 = acc5[nt][0] + b50, z1 = acc5[nt][1] + b51;
         const float V = 1.0f / (1.0f + expf(-z0));
-        const float U = fmaxf(z1, 0.f) + log1pf(expf(-fabsf(z1)));
+        const float U = z1;   // predicted |T - V|, linear (no saturating activation)
         if (kMode != kModeTrain) {
             if (g == 0 && valid) {
                 a.vis[s] = V;
@@ -305,14 +305,14 @@ __device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
             const float e = fabsf(T - V);
             const float inv_n = 1.0f / (float)a.n;
             const float dz0 = (V - T) * inv_n;
-            const float sg = (U > e) ? 1.f : (U < e) ? -1.f : 0.f;
-            const float dz1 = sg * (1.0f / (1.0f + expf(-z1))) * inv_n;
+            // squared error of U against |T - V| (V held constant)
+            const float dz1 = 2.0f * (U - e) * inv_n;
             if (g == 0) {
                 a.dz5[s] = valid ? (uint16_t)bf16_bits(dz0) : (uint16_t)0;
                 a.dz5[a.stride + s] = valid ? (uint16_t)bf16_bits(dz1) : (uint16_t)0;
                 if (valid) {
                     const float bce = -(T * logf(fmaxf(V, 1e-12f)) + (1.f - T) * logf(fmaxf(1.f - V, 1e-12f)));
-                    lsum += bce + fabsf(U - e);
+                    lsum += bce + (U - e) * (U - e);
                 }
             }
         }

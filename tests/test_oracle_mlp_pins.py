@@ -101,8 +101,9 @@ def test_forward_ranges_and_init_shapes():
     theta = mlp_init.he_uniform(7)
     assert theta.size == mlp.n_params() == 214530
     x, d, T = _data(100, 4)
-    V, U, _ = mlp.forward(theta, x, d, -2 * np.ones(3), 2 * np.ones(3))
-    assert np.all((V > 0) & (V < 1)) and np.all(U >= 0)
+    V, U, c = mlp.forward(theta, x, d, -2 * np.ones(3), 2 * np.ones(3))
+    # V is a probability; U is the head's second output itself (linear)
+    assert np.all((V > 0) & (V < 1)) and np.array_equal(U, c["zs"][-1][:, 1])
 
 
 # Error scales of a BF16/FP32 evaluation: the network run with binary32
@@ -139,11 +140,11 @@ def _f32_network(theta, x, d, T, lo, hi):
     z5 = zs[-1]
     n = x.shape[0]
     V = (1 / (1 + np.exp(-z5[:, 0]))).astype(np.float32)
-    U = (np.maximum(z5[:, 1], 0) + np.log1p(np.exp(-np.abs(z5[:, 1])))).astype(np.float32)
+    U = z5[:, 1]
     e = np.abs(T.astype(np.float32) - V)
     dz = np.zeros((n, 2), np.float32)
     dz[:, 0] = (V - T) / np.float32(n)
-    dz[:, 1] = np.sign(U - e) / (1 + np.exp(-z5[:, 1])) / np.float32(n)
+    dz[:, 1] = np.float32(2) * (U - e) / np.float32(n)
     grads = [None] * len(layers)
     for li in range(len(layers) - 1, -1, -1):
         dzr = bf(dz)
