@@ -204,6 +204,28 @@ rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g, const floa
                               size_t ws_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rv_trace_visibility with its scratch (the work-queue counters, and the
+ * per-ray values when vis_ray is NULL) taken from a static array that the
+ * library holds on each device it runs on until the process ends, of
+ * rv_trace_static_scratch_bytes() = 32 MiB. The call allocates nothing; the
+ * caller passes the inputs and outputs as for rv_trace_visibility and gets the
+ * same bits. Without vis_ray, n*K must be at most (32 MiB - 256) / 4 =
+ * 8,388,544 rays, else RV_ERR_WORKSPACE and nothing is enqueued; with vis_ray
+ * any size is accepted. Every call on a device shares that device's array:
+ * calls that overlap on one device (on different streams, or from several
+ * threads) race and give undefined results; calls on one stream are ordered.
+ * The counters are cleared by a kernel at the start of every call (never a
+ * memset, so the call can be captured in a graph).
+ * Errors: as rv_trace_visibility, RV_ERR_WORKSPACE (size beyond the scratch),
+ * RV_ERR_HIP (no current device, or the scratch could not be located).
+ */
+size_t rv_trace_static_scratch_bytes(void);
+rv_status rv_trace_visibility_static(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
+                                     const rv_trace_params *p, float *vis_ray, float *vis_mean, void *stream);
+
+/*
  * Trace an explicit list of ray ids (device int64 [n_rays], r = i*K + k) and
  * write out[s] = T of ray ids[s]. Gives the same bits as rv_trace_visibility
  * for the same ray.

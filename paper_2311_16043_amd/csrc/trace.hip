@@ -17,6 +17,7 @@
 // its own T; per-Gaussian means are FP64 row sums in a fixed order
 // (deterministic, no atomics).
 #include <atomic>
+#include <mutex>
 #include <type_traits>
 
 #include "trace_core.h"
@@ -1007,6 +1008,52 @@ void launch_trace_stream(const void *bvh, const rv_gaussians *g, const float *di
                        K, c, m_lo, m_hi, by_leaf ? 1 : 0, queues, vis_ray, totals);
 }
 
+// Enqueue the all-ray trace with its scratch at ws (256-byte aligned: the
+// queue counters, then the per-ray values when vis_ray is NULL).
+void trace_visibility_into(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
+                           const rv_trace_params *p, float *vis_ray, float *vis_mean, void *ws, hipStream_t s) {
+    // the per-ray values go to vis_ray, else to the workspace after the queues
+    float *rays = vis_ray ? vis_ray : reinterpret_cast<float *>(static_cast<char *>(ws) + kAlign);
+    launch_trace_stream<false>(bvh, g, dirs, K, make_cuts(*p), ws, rays, nullptr, s);
+    if (vis_mean) {
+        const int64_t blocks = std::min<int64_t>((g->n + 3) / 4, int64_t(1) << 20);
+        hipLaunchKernelGGL(k_mean_rows, dim3((unsigned)blocks), dim3(256), 0, s, rays, g->n, K, vis_mean);
+    }
+}
+
+// ---- scratch of the allocation-free entry point ---------------------------
+//
+// One array per device, held until the process ends: the queue counters and,
+// for calls without per-ray output, the per-ray values. In host code the
+// array's name is a host-side stand-in, never a device address: its device
+// address is looked up once per device (with that device current) and only
+// that address is passed on.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch (looked up on its first use).
+rv_status static_scratch(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    RV_REQUIRE(e == hipSuccess && dev >= 0 && dev < kMaxDevices, RV_ERR_HIP,
+               "rv_trace_visibility_static: no current device (HIP error %d)", (int)e);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        RV_REQUIRE(e == hipSuccess && ptr, RV_ERR_HIP,
+                   "rv_trace_visibility_static: hipGetSymbolAddress of the scratch failed on device %d: %s", dev,
+                   hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RV_OK;
+}
+
 }  // namespace
 
 extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
@@ -1020,15 +1067,29 @@ extern "C" rv_status rv_trace_visibility(const void *bvh, const rv_gaussians *g,
                "rv_trace_visibility: needs a 256-byte aligned workspace");
     const size_t need = vis_ray ? kAlign : rv_trace_workspace_bytes(g->n, K);
     RV_REQUIRE(ws_bytes >= need, RV_ERR_WORKSPACE, "rv_trace_visibility: ws_bytes %zu < %zu", ws_bytes, need);
-    // the per-ray values go to vis_ray, else to the workspace after the queues
-    float *rays = vis_ray ? vis_ray : reinterpret_cast<float *>(static_cast<char *>(ws) + kAlign);
-    hipStream_t s = (hipStream_t)stream;
-    launch_trace_stream<false>(bvh, g, dirs, K, make_cuts(*p), ws, rays, nullptr, s);
-    if (vis_mean) {
-        const int64_t blocks = std::min<int64_t>((g->n + 3) / 4, int64_t(1) << 20);
-        hipLaunchKernelGGL(k_mean_rows, dim3((unsigned)blocks), dim3(256), 0, s, rays, g->n, K, vis_mean);
-    }
+    trace_visibility_into(bvh, g, dirs, K, p, vis_ray, vis_mean, ws, (hipStream_t)stream);
     return check_launch("rv_trace_visibility");
+}
+
+extern "C" size_t rv_trace_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+extern "C" rv_status rv_trace_visibility_static(const void *bvh, const rv_gaussians *g, const float *dirs,
+                                                int32_t K, const rv_trace_params *p, float *vis_ray,
+                                                float *vis_mean, void *stream) {
+    clear_error();
+    rv_status st = validate_trace("rv_trace_visibility_static", bvh, g, dirs, K, p);
+    if (st != RV_OK) return st;
+    RV_REQUIRE(vis_ray || vis_mean, RV_ERR_INVALID_ARG, "rv_trace_visibility_static: both outputs are NULL");
+    const size_t need = vis_ray ? kAlign : rv_trace_workspace_bytes(g->n, K);
+    RV_REQUIRE(need <= kStaticScratchBytes, RV_ERR_WORKSPACE,
+               "rv_trace_visibility_static: without vis_ray the %lld x %d per-ray values need %zu bytes of scratch, "
+               "more than the %zu-byte static scratch (at most %zu rays; pass vis_ray or use rv_trace_visibility)",
+               (long long)g->n, K, need, kStaticScratchBytes, (kStaticScratchBytes - kAlign) / sizeof(float));
+    void *ws = nullptr;
+    st = static_scratch(&ws);
+    if (st != RV_OK) return st;
+    trace_visibility_into(bvh, g, dirs, K, p, vis_ray, vis_mean, ws, (hipStream_t)stream);
+    return check_launch("rv_trace_visibility_static");
 }
 
 extern "C" rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,

@@ -188,6 +188,24 @@ def trace_visibility(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = 
     return vr, vm
 
 
+def trace_visibility_static(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = None,
+                            out_ray: torch.Tensor | None = None, out_mean: torch.Tensor | None = None):
+    """trace_visibility into caller-given outputs (either may be None, not
+    both), with the library's static per-device scratch instead of a
+    workspace: the library call allocates nothing. Calls that overlap on one
+    device race; calls on one stream are ordered."""
+    check_pair(bvh, g, "trace_visibility_static")
+    if out_ray is None and out_mean is None:
+        raise ValueError("trace_visibility_static: give out_ray, out_mean or both")
+    params = params or TraceParams()
+    d = _dirs(dirs, g.mean.device)
+    gc, pc = g.c(), params.c()
+    _lib.call("rv_trace_visibility_static", bvh.ptr, C.byref(gc), d.data_ptr(), int(d.shape[0]), C.byref(pc),
+              None if out_ray is None else out_ray.data_ptr(), None if out_mean is None else out_mean.data_ptr(),
+              _stream_ptr(g.mean.device))
+    return out_ray, out_mean
+
+
 def trace_visibility_sh(bvh: BVH, g: Gaussians, dirs, params: TraceParams | None = None, want_mean: bool = True,
                         workspace: torch.Tensor | None = None):
     """(vis_sh [n, 9], vis_mean [n] or None): each Gaussian's visibility
