@@ -206,12 +206,11 @@ __device__ __forceinline__ void store_act(uint16_t *__restrict__ ht, int64_t str
 // A wave handles NT tiles of 16 samples (two in training, three in
 // inference); several waves share a SIMD, so one wave's vector work overlaps
 // the others' matrix products.
-template <int kMode, int NT = 2>
-__device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t s_base = a.s_off + wave * (16 * NT);
-    if (s_base >= a.n) return;  // wave-uniform
+// The encoded inputs of NT tiles of 16 samples from s_base as B operands
+// (k-blocks 0 and 1 of act; features kfeat), and the targets in training.
+template <int kMode, int NT>
+__device__ __forceinline__ void encode_tiles(const FwdArgs &a, int64_t s_base, int lane, u32x4 (&act)[8][NT],
+                                             float (&Tv)[NT]) {
     const int g = lane >> 4, col = lane & 15;
     const float lo0 = a.header[0], lo1 = a.header[1], lo2 = a.header[2];
     const float hi0 = a.header[3], hi1 = a.header[4], hi2 = a.header[5];
@@ -220,8 +219,6 @@ __device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
         return span > 0.f ? 2.0f * (x - lo) / span - 1.0f : 0.0f;
     };
 
-    u32x4 act[8][NT];
-    float Tv[NT] = {};
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int64_t s = s_base + nt * 16 + col;
@@ -262,6 +259,18 @@ __device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
                 act[kb][nt][w] = pack2(enc_feature(kfeat(kb, g, 2 * w), u0, u1, u2, d0, d1, d2),
                                        enc_feature(kfeat(kb, g, 2 * w + 1), u0, u1, u2, d0, d1, d2));
     }
+}
+
+template <int kMode, int NT = 2>
+__device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t s_base = a.s_off + wave * (16 * NT);
+    if (s_base >= a.n) return;  // wave-uniform
+    const int g = lane >> 4, col = lane & 15;
+    u32x4 act[8][NT];
+    float Tv[NT] = {};
+    encode_tiles<kMode, NT>(a, s_base, lane, act, Tv);
     if (kMode == kModeTrain) store_act<2, NT>(a.ht + ht_row(0) * a.stride, a.stride, act, lane, s_base, a.n);
 
     const float *master = a.master;
@@ -323,17 +332,175 @@ __device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
     }
 }
 
-// Inference: 48 samples per wave (three tiles), two waves per SIMD at 234
-// VGPRs. Each weight fragment fetched through the L1 now serves 48 samples
-// instead of 32, which the vector-memory path limits (31.5 against 34.2 ms at
-// object scale). Training keeps two tiles: the saved activations need the
-// registers.
-template <int kMode>
-__global__ __launch_bounds__(256, 2) void k_mlp_forward(FwdArgs a) {
-    mlp_forward_body<kMode, 3>(a);
+__global__ __launch_bounds__(256, 2) void k_mlp_forward_train(FwdArgs a) { mlp_forward_body<kModeTrain>(a); }
+
+// ---- inference with the weights staged through LDS ------------------------------
+//
+// Inference takes 32 samples per wave (two tiles) and eight waves per block,
+// one block per CU (two waves per SIMD). The waves of a block share every
+// weight fragment: the packed A operands are streamed layer by layer, in
+// chunks of at most 64 KB, into one of two LDS buffers by direct
+// global-to-LDS loads (no registers held), the next chunk loading while the
+// current one is multiplied, one barrier per chunk (eight per 256 samples).
+// Every A operand is then read from LDS. When each wave fetched all 424 KB of
+// packed weights itself (48 samples per wave), those fetches ran at the rate
+// of the CU's vector-memory path (TD busy 96 %) and held the matrix cores at
+// 42 % of peak. Three tiles per wave do not fit 256 registers next to the LDS
+// pipeline (the compiler spills ~150).
+constexpr int kInferWaves = 8;
+constexpr int kInferNT = 2;
+constexpr int kInferSamples = kInferWaves * 16 * kInferNT;  // 256 per block
+constexpr int kChunkVec = 4096;                             // 16-byte vectors per LDS buffer (64 KB)
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// This wave's share of copying `count` vectors (a multiple of 64) of packed
+// operands from src to the LDS buffer dst: the 1 KB pieces wv, wv + 8, ...
+// (a global_load_lds_dwordx4 writes 16 bytes per lane from the wave's LDS base).
+__device__ __forceinline__ void load_chunk(const u32x4 *__restrict__ src, int count, u32x4 *dst, int wv, int lane) {
+    for (int p = wv; p < count / 64; p += kInferWaves)
+        __builtin_amdgcn_global_load_lds(static_cast<const void *>(src + p * 64 + lane),
+                                         (lds_void *)(dst + p * 64), 16, 0, 0);
 }
 
-__global__ __launch_bounds__(256, 2) void k_mlp_forward_train(FwdArgs a) { mlp_forward_body<kModeTrain>(a); }
+// This wave's loads into LDS have landed, then every wave's have, and every
+// wave has finished reading the buffer the next loads will overwrite.
+__device__ __forceinline__ void chunk_barrier() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Output pair OP0 + o of a layer (the same arithmetic as hidden_layer) from
+// the LDS chunk holding the A operands of pairs OP0, OP0 + 1, ...
+template <int KB, int NT, int OP0>
+__device__ __forceinline__ void layer_ops_lds_one(const u32x4 *A, int o, const float *__restrict__ bias,
+                                                  const u32x4 (&act)[8][NT], u32x4 (&out)[8][NT], int lane) {
+    const int g = lane >> 4;
+    f32x4 acc[2][NT];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[h][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const u32x4 a0 = A[((2 * o) * KB + kb) * 64 + lane];
+        const u32x4 a1 = A[((2 * o + 1) * KB + kb) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            acc[0][nt] = mfma16(a0, act[kb][nt], acc[0][nt]);
+            acc[1][nt] = mfma16(a1, act[kb][nt], acc[1][nt]);
+        }
+        // per k-block: its two LDS reads, then its products
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 2 * NT, 0);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const float4 bv = *reinterpret_cast<const float4 *>(bias + (2 * (OP0 + o) + h) * 16 + 4 * g);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const float h0 = fmaxf(acc[h][nt][0] + bv.x, 0.f), h1 = fmaxf(acc[h][nt][1] + bv.y, 0.f);
+            const float h2 = fmaxf(acc[h][nt][2] + bv.z, 0.f), h3 = fmaxf(acc[h][nt][3] + bv.w, 0.f);
+            out[OP0 + o][nt][2 * h + 0] = pack2(h0, h1);
+            out[OP0 + o][nt][2 * h + 1] = pack2(h2, h3);
+        }
+    }
+}
+
+// A 256 -> 256 layer from two LDS chunks (output pairs 0-3, then 4-7);
+// `between` runs once the first half is done (the chunk hand-over). The
+// output array is local, as in hidden_layer, so the input array's registers
+// are reused as soon as the layer ends.
+// Output pairs [OP0, OP0 + NOP) of a layer from one LDS chunk.
+template <int KB, int NT, int OP0, int NOP>
+__device__ __forceinline__ void layer_ops_lds(const u32x4 *A, const float *__restrict__ bias,
+                                              const u32x4 (&act)[8][NT], u32x4 (&out)[8][NT], int lane) {
+#pragma unroll
+    for (int o = 0; o < NOP; ++o) layer_ops_lds_one<KB, NT, OP0>(A, o, bias, act, out, lane);
+}
+
+template <int NT, class Between>
+__device__ __forceinline__ void hidden_layer_lds(const u32x4 *A_lo, const u32x4 *A_hi, const float *__restrict__ bias,
+                                                 u32x4 (&act)[8][NT], int lane, Between between) {
+    u32x4 out[8][NT];
+    layer_ops_lds<8, NT, 0, 4>(A_lo, bias, act, out, lane);
+    between();
+    layer_ops_lds<8, NT, 4, 4>(A_hi, bias, act, out, lane);
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) act[kb][nt] = out[kb][nt];
+}
+
+// Chunks, in 16-byte vectors of the packed forward operands: layer 1 whole
+// (2,048), layers 2-4 in halves of four output pairs (4,096 each), the head
+// (512). Chunk c is multiplied from buffer c % 2 while chunk c + 1 loads into
+// the other. A k-block's two LDS reads are scheduled right before its
+// products: hoisted further, as the compiler otherwise does, they spill the
+// activations.
+template <int kMode>
+__global__ __launch_bounds__(kInferWaves * 64, 1) void k_mlp_forward(FwdArgs a) {
+    constexpr int NT = kInferNT;
+    __shared__ u32x4 wbuf[2][kChunkVec];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    // every wave takes part in the loads and barriers; waves past the end
+    // encode zeros and write nothing
+    const int64_t s_base = a.s_off + ((int64_t)blockIdx.x * kInferWaves + wv) * (16 * NT);
+    const u32x4 *F = a.fwd;
+    const float *master = a.master;
+    load_chunk(F + fwd_off(0) / 8, 2048, wbuf[0], wv, lane);
+    u32x4 act[8][NT];
+    float Tv[NT] = {};
+    encode_tiles<kMode, NT>(a, s_base, lane, act, Tv);
+    chunk_barrier();
+    // layer 1 (64 -> 256) from buffer 0; layer 2's first half loads into buffer 1
+    load_chunk(F + fwd_off(1) / 8, kChunkVec, wbuf[1], wv, lane);
+    {
+        u32x4 out[8][NT];
+        layer_ops_lds<2, NT, 0, 8>(wbuf[0], master + off_b(0), act, out, lane);
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) act[kb][nt] = out[kb][nt];
+    }
+    chunk_barrier();
+    // layers 2-4, each from buffer 1 (first half) then buffer 0 (second half)
+    // while the following chunk loads into the other buffer
+#pragma unroll
+    for (int l = 1; l <= 3; ++l) {
+        load_chunk(F + fwd_off(l) / 8 + kChunkVec, kChunkVec, wbuf[0], wv, lane);
+        hidden_layer_lds<NT>(wbuf[1], wbuf[0], master + off_b(l), act, lane, [&]() {
+            chunk_barrier();
+            if (l < 3) load_chunk(F + fwd_off(l + 1) / 8, kChunkVec, wbuf[1], wv, lane);
+            else load_chunk(F + fwd_off(4) / 8, 512, wbuf[1], wv, lane);
+        });
+        chunk_barrier();
+    }
+    // head: one block of 16 outputs, rows 0 and 1 are z0, z1
+    f32x4 acc5[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc5[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+        const u32x4 av = wbuf[1][kb * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc5[nt] = mfma16(av, act[kb][nt], acc5[nt]);
+    }
+    const float b50 = master[off_b(4)], b51 = master[off_b(4) + 1];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int64_t s = s_base + nt * 16 + col;
+        if (g == 0 && s < a.n) {
+            const float z0 = acc5[nt][0] + b50, z1 = acc5[nt][1] + b51;
+            const float V = 1.0f / (1.0f + expf(-z0));
+            const float U = z1;
+            a.vis[s] = V;
+            if (a.unc) a.unc[s] = U;
+            if (kMode == kModeGrid && a.fb_flag) a.fb_flag[s] = U > a.tau ? 1 : 0;
+        }
+    }
+}
 
 // ---- backward through the layers ----------------------------------------------
 
@@ -897,7 +1064,7 @@ extern "C" rv_status rv_surrogate_infer_xd(const void *params, const float *x, c
     for (int64_t off = 0; off < n; off += kLaunchSamples) {
         fa.s_off = off;
         const int64_t cnt = std::min(kLaunchSamples, n - off);
-        hipLaunchKernelGGL(k_mlp_forward<kModeXd>, dim3(blocks_for((cnt + 47) / 48, 4)), dim3(256), 0,
+        hipLaunchKernelGGL(k_mlp_forward<kModeXd>, dim3(blocks_for(cnt, kInferSamples)), dim3(kInferWaves * 64), 0,
                            (hipStream_t)stream, fa);
     }
     return check_launch("rv_surrogate_infer_xd");
@@ -946,7 +1113,8 @@ extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, con
     for (int64_t off = 0; off < q_count; off += kLaunchSamples) {
         fa.s_off = off;
         const int64_t cnt = std::min(kLaunchSamples, q_count - off);
-        hipLaunchKernelGGL(k_mlp_forward<kModeGrid>, dim3(blocks_for((cnt + 47) / 48, 4)), dim3(256), 0, s, fa);
+        hipLaunchKernelGGL(k_mlp_forward<kModeGrid>, dim3(blocks_for(cnt, kInferSamples)), dim3(kInferWaves * 64), 0,
+                           s, fa);
     }
     if (bvh) {
         const Cuts c = make_cuts(*p);
