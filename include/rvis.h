@@ -283,6 +283,16 @@ rv_status rv_trace_stats(const void *bvh, const rv_gaussians *g, const float *di
 rv_status rv_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /*
+ * Read-only streaming probe: reads `bytes` (a positive multiple of 16;
+ * 16-byte aligned src) once with non-temporal loads; each thread stores the
+ * XOR of what it read to sink (device uint32 [rv_stream_read_sink_words(bytes)]).
+ * The achievable read bandwidth: the denominator for kernels whose HBM
+ * traffic is reads. Errors: RV_ERR_INVALID_ARG, RV_ERR_HIP.
+ */
+size_t rv_stream_read_sink_words(size_t bytes);
+rv_status rv_stream_read(const void *src, size_t bytes, uint32_t *sink, void *stream);
+
+/*
  * Record-gather probe: the achievable rate of the traversal's memory access
  * pattern, measured rather than assumed. table: device, n_records records of
  * 64 bytes (16-byte aligned); each of blocks x 256 threads reads `rounds`

@@ -8,7 +8,7 @@ provides device memory and streams only.
 from ._lib import RvError, load  # noqa: F401
 from .tracer import (BVH, Gaussians, TraceParams, build_bvh, refit_bvh, trace_rays, trace_stats,  # noqa: F401
                      trace_visibility, trace_visibility_backward, trace_visibility_sh, stream_copy,
-                     gather_probe)
+                     gather_probe, stream_read)
 from .autograd import VisibilityFn, visibility  # noqa: F401
 from .surrogate import Surrogate, ray_setup  # noqa: F401
 from .shading import shade_pbr  # noqa: F401

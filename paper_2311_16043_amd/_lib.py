@@ -78,6 +78,8 @@ SIGNATURES = {
     "rv_trace_visibility_backward": (_i32, [_vp, _PG, _vp, _i32, _PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rv_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
     "rv_gather_probe": (_i32, [_vp, _i64, _i32, _i32, _vp, _vp]),
+    "rv_stream_read_sink_words": (_sz, [_sz]),
+    "rv_stream_read": (_i32, [_vp, _sz, _vp, _vp]),
     "rv_trace_static_scratch_bytes": (_sz, []),
     "rv_trace_visibility_static": (_i32, [_vp, _PG, _vp, _i32, _PP, _vp, _vp, _vp]),
     "rv_surrogate_n_params": (_i64, []),

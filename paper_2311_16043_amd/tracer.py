@@ -305,3 +305,12 @@ def gather_probe(table: torch.Tensor, rounds: int, blocks: int) -> torch.Tensor:
     _lib.call("rv_gather_probe", table.data_ptr(), nbytes // 64, int(rounds), int(blocks), sink.data_ptr(),
               _stream_ptr(table.device))
     return sink
+
+
+def stream_read(src: torch.Tensor) -> torch.Tensor:
+    """Read src once with the library's streaming read probe; returns the sink."""
+    nbytes = src.numel() * src.element_size()
+    words = int(_lib.load().rv_stream_read_sink_words(nbytes))
+    sink = torch.empty(words, dtype=torch.int32, device=src.device)
+    _lib.call("rv_stream_read", src.data_ptr(), nbytes, sink.data_ptr(), _stream_ptr(src.device))
+    return sink
