@@ -100,9 +100,9 @@ def parse():
     ap.add_argument("--no-shade", action="store_true", help="skip the PBR shading leg")
     ap.add_argument("--no-sh", action="store_true", help="skip the SH-compressed visibility leg")
     ap.add_argument("--sur-train-samples", type=int, default=50_000_000)
-    ap.add_argument("--sur-steps", type=int, default=18312,
-                    help="optimiser steps (18312 x 16384 = six passes over 50M; the fallback needed for MAE 0.02 "
-                         "falls with the number of steps: 63 %% after two passes, 54 %% after four)")
+    ap.add_argument("--sur-steps", type=int, default=24416,
+                    help="optimiser steps (24416 x 16384 = eight passes over 50M; the fallback needed for MAE 0.02 "
+                         "falls with the number of steps: 63 %% after two passes, 54 %% after four, 52 %% after six)")
     ap.add_argument("--sur-batch", type=int, default=16384)
     ap.add_argument("--sur-mae", type=float, default=0.02, help="target mean absolute visibility error")
     return ap.parse_args()
@@ -164,8 +164,9 @@ def surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, plain_rays_per_s):
     order = torch.argsort(uh, descending=True)
     e_sorted = err[order]
     kept_err = torch.flip(torch.cumsum(torch.flip(e_sorted, [0]), 0), [0]) / err.numel()  # MAE if the first j are traced
-    # a 5 % margin so that the error over all queries stays within the target
-    ok = torch.nonzero(kept_err <= 0.95 * args.sur_mae)
+    # a 2.5 % margin so that the error over all queries stays within the
+    # target (the standard error of the held-out estimate is ~0.5 % of it)
+    ok = torch.nonzero(kept_err <= 0.975 * args.sur_mae)
     j = int(ok[0]) if ok.numel() else err.numel()
     tau = float(uh[order[j]]) if j < err.numel() else float("-inf")
     corr = float(torch.corrcoef(torch.stack([uh, err]))[0, 1])
@@ -370,7 +371,9 @@ def cpu_baseline(scene, dirs, dir_mode, target_s, target1_s):
         t = time.perf_counter()
         oracle.trace_rays(scene, dirs, dir_mode, scenes.sample_ray_ids(n, K, 1, seed=98))
         setup = time.perf_counter() - t
-        pilot = scenes.sample_ray_ids(n, K, max(16, min(512, 512 * 300_000 // n)), seed=99)
+        # the oracle hands rays to its threads 16 at a time: a pilot of fewer
+        # than 16 rays per thread leaves threads idle and overstates the cost
+        pilot = scenes.sample_ray_ids(n, K, max(16 * oracle.threads(), min(512, 512 * 300_000 // n)), seed=99)
         t = time.perf_counter()
         oracle.trace_rays(scene, dirs, dir_mode, pilot)
         per_ray = max(time.perf_counter() - t - setup, 1e-3) / pilot.size
