@@ -133,73 +133,85 @@ struct FwdArgs {
     uint8_t *fb_flag;  // per query: 1 = to be traced (grid mode with a BVH), else NULL
 };
 
+// Training takes the batch in blocks of kTrainNT 16-sample tiles, each block
+// kTrainWaves waves that split every layer's outputs (kTrainOps k-blocks of
+// the next layer's input per wave), and covers the batch rounded up to 32
+// samples: the padded samples' activations and gradients are stored as zeros
+// for the weight-gradient products, which step over 32 samples at a time.
+constexpr int kTrainWaves = 8, kTrainNT = 2;
+constexpr int kTrainOps = 8 / kTrainWaves;
+constexpr int64_t kTrainPad = 16 * kTrainNT > 32 ? 16 * kTrainNT : 32;
+static_assert(kTrainWaves * kTrainOps == 8 && kTrainPad % (16 * kTrainNT) == 0 && kTrainPad <= 128,
+              "training block shape");
+__host__ __device__ constexpr int64_t train_pad(int64_t n) { return ((n + kTrainPad - 1) / kTrainPad) * kTrainPad; }
+
 // feature-major activation sections: HT0 (64 rows), HT1..HT4 (256 rows each)
 __host__ __device__ constexpr int64_t ht_row(int j) { return j == 0 ? 0 : 64 + (int64_t)(j - 1) * 256; }
 constexpr int64_t kHtRows = 64 + 4 * 256;
 constexpr int64_t kDzRows = 4 * 256 + 16;  // dZ1..dZ4 (256 rows each), dZ5 (2 rows, 16 reserved)
 __host__ __device__ constexpr int64_t dz_row(int l) { return l < 4 ? (int64_t)l * 256 : 1024; }  // l = 0..4
 
-// One hidden layer for NT tiles of 16 samples: act (B operands, kb-blocks of
-// the input) -> act (the ReLU outputs, as B operands of the next layer). The
-// outputs are produced two 16-row blocks at a time (one B-operand block of
-// the next layer), so only 2 NT accumulators are live and the bias, ReLU and
-// bf16 conversion of one pair overlap the products of the next.
+// Output blocks 2 op and 2 op + 1 of a hidden layer for NT 16-sample tiles:
+// act (B operands, k-blocks of the input) -> the ReLU outputs as k-block op of
+// the next layer's B operand (bias, ReLU, one v_cvt_pk_bf16_f32 per pair).
 template <int KB, int NT>
-__device__ __forceinline__ void hidden_layer(const u32x4 *__restrict__ A, const float *__restrict__ bias,
-                                             u32x4 (&act)[8][NT], int lane) {
+__device__ __forceinline__ void fwd_pair(const u32x4 *__restrict__ A, const float *__restrict__ bias,
+                                         const u32x4 (&act)[8][NT], int op, int lane, u32x4 (&out)[NT]) {
     const int g = lane >> 4;
-    u32x4 out[8][NT];
+    f32x4 acc[2][NT];
 #pragma unroll
-    for (int op = 0; op < 8; ++op) {
-        f32x4 acc[2][NT];
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int nt = 0; nt < NT; ++nt) acc[h][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[h][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < KB; ++kb) {
+        const u32x4 a0 = A[((2 * op) * KB + kb) * 64 + lane];
+        const u32x4 a1 = A[((2 * op + 1) * KB + kb) * 64 + lane];
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            const u32x4 a0 = A[((2 * op) * KB + kb) * 64 + lane];
-            const u32x4 a1 = A[((2 * op + 1) * KB + kb) * 64 + lane];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                acc[0][nt] = mfma16(a0, act[kb][nt], acc[0][nt]);
-                acc[1][nt] = mfma16(a1, act[kb][nt], acc[1][nt]);
-            }
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const float4 bv = *reinterpret_cast<const float4 *>(bias + (2 * op + h) * 16 + 4 * g);
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const float h0 = fmaxf(acc[h][nt][0] + bv.x, 0.f), h1 = fmaxf(acc[h][nt][1] + bv.y, 0.f);
-                const float h2 = fmaxf(acc[h][nt][2] + bv.z, 0.f), h3 = fmaxf(acc[h][nt][3] + bv.w, 0.f);
-                out[op][nt][2 * h + 0] = pack2(h0, h1);
-                out[op][nt][2 * h + 1] = pack2(h2, h3);
-            }
+        for (int nt = 0; nt < NT; ++nt) {
+            acc[0][nt] = mfma16(a0, act[kb][nt], acc[0][nt]);
+            acc[1][nt] = mfma16(a1, act[kb][nt], acc[1][nt]);
         }
     }
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
+    for (int h = 0; h < 2; ++h) {
+        const float4 bv = *reinterpret_cast<const float4 *>(bias + (2 * op + h) * 16 + 4 * g);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) act[kb][nt] = out[kb][nt];
+        for (int nt = 0; nt < NT; ++nt) {
+            out[nt][2 * h + 0] = pack2(fmaxf(acc[h][nt][0] + bv.x, 0.f), fmaxf(acc[h][nt][1] + bv.y, 0.f));
+            out[nt][2 * h + 1] = pack2(fmaxf(acc[h][nt][2] + bv.z, 0.f), fmaxf(acc[h][nt][3] + bv.w, 0.f));
+        }
+    }
 }
 
-// Store the B-operand blocks [0, KB) of act as feature-major rows of ht.
-template <int KB, int NT>
-__device__ __forceinline__ void store_act(uint16_t *__restrict__ ht, int64_t stride, const u32x4 (&act)[8][NT],
-                                          int lane, int64_t s_base, int64_t n) {
+// The word of the lane next to this one (lanes 2c and 2c+1 swap): one DPP
+// quad permute [1, 0, 3, 2].
+__device__ __forceinline__ uint32_t pair_swap(uint32_t w) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xB1, 0xF, 0xF, false);
+}
+
+// Feature-major rows are written and read two samples (one 32-bit word) per
+// lane: in a word holding rows ra (low halves) and rb (high halves) of this
+// lane's sample, the even lane of a pair (samples s, s + 1) takes row ra of
+// both samples and the odd lane (samples s - 1, s) row rb of both.
+__device__ __forceinline__ uint32_t pair_row_word(uint32_t own, bool odd) {
+    const uint32_t nb = pair_swap(own);
+    return odd ? ((nb >> 16) | (own & 0xffff0000u)) : ((own & 0xffffu) | (nb << 16));
+}
+
+// Store k-block kb of a tile's B operand (features kfeat(kb, ., .)) as
+// feature-major rows of ht, samples at or past n as zeros.
+__device__ __forceinline__ void store_kblock(uint16_t *__restrict__ ht, int64_t stride, const u32x4 &frag, int kb,
+                                             int lane, int64_t s_base, int64_t n) {
     const int g = lane >> 4, col = lane & 15;
+    const bool odd = col & 1;
+    const int64_t s2 = s_base + (col & ~1);   // first sample of the lane pair
+    const uint32_t keep = (s2 < n ? 0x0000ffffu : 0u) | (s2 + 1 < n ? 0xffff0000u : 0u);
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int64_t s = s_base + nt * 16 + col;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-            for (int sl = 0; sl < 8; ++sl) {
-                const uint32_t w = act[kb][nt][sl >> 1];
-                const uint16_t b = (uint16_t)((sl & 1) ? (w >> 16) : (w & 0xffffu));
-                ht[(int64_t)kfeat(kb, g, sl) * stride + s] = s < n ? b : (uint16_t)0;
-            }
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t word = pair_row_word(frag[w], odd) & keep;
+        const int f = kfeat(kb, g, 2 * w + (odd ? 1 : 0));
+        *reinterpret_cast<uint32_t *>(ht + (int64_t)f * stride + s2) = word;
     }
 }
 
@@ -261,27 +273,55 @@ __device__ __forceinline__ void encode_tiles(const FwdArgs &a, int64_t s_base, i
     }
 }
 
-template <int kMode, int NT = 2>
-__device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t s_base = a.s_off + wave * (16 * NT);
-    if (s_base >= a.n) return;  // wave-uniform
+// Training forward: one block of kTrainWaves waves per kTrainNT 16-sample
+// tiles. Wave w produces output blocks of k-blocks kTrainOps w .. kTrainOps
+// (w + 1) - 1 of every hidden layer's output (the next layer's input) and
+// stores them as feature-major rows; the waves exchange each layer's output
+// through LDS (double-buffered, one barrier per layer). Wave 0 evaluates the
+// head and the loss.
+__global__ __launch_bounds__(kTrainWaves * 64, 16 / kTrainWaves) void k_mlp_forward_train(FwdArgs a) {
+    constexpr int NT = kTrainNT;
+    __shared__ u32x4 xb[2][8][NT][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t s_base = tile * (16 * NT);
+    if (s_base >= train_pad(a.n)) return;  // block-uniform
     const int g = lane >> 4, col = lane & 15;
     u32x4 act[8][NT];
     float Tv[NT] = {};
-    encode_tiles<kMode, NT>(a, s_base, lane, act, Tv);
-    if (kMode == kModeTrain) store_act<2, NT>(a.ht + ht_row(0) * a.stride, a.stride, act, lane, s_base, a.n);
-
+    encode_tiles<kModeTrain, NT>(a, s_base, lane, act, Tv);
+    if (w < 2) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            store_kblock(a.ht + ht_row(0) * a.stride, a.stride, w == 0 ? act[0][nt] : act[1][nt], w, lane,
+                         s_base + 16 * nt, a.n);
+    }
     const float *master = a.master;
-    hidden_layer<2, NT>(a.fwd + fwd_off(0) / 8, master + off_b(0), act, lane);
-    if (kMode == kModeTrain) store_act<8, NT>(a.ht + ht_row(1) * a.stride, a.stride, act, lane, s_base, a.n);
-    hidden_layer<8, NT>(a.fwd + fwd_off(1) / 8, master + off_b(1), act, lane);
-    if (kMode == kModeTrain) store_act<8, NT>(a.ht + ht_row(2) * a.stride, a.stride, act, lane, s_base, a.n);
-    hidden_layer<8, NT>(a.fwd + fwd_off(2) / 8, master + off_b(2), act, lane);
-    if (kMode == kModeTrain) store_act<8, NT>(a.ht + ht_row(3) * a.stride, a.stride, act, lane, s_base, a.n);
-    hidden_layer<8, NT>(a.fwd + fwd_off(3) / 8, master + off_b(3), act, lane);
-    if (kMode == kModeTrain) store_act<8, NT>(a.ht + ht_row(4) * a.stride, a.stride, act, lane, s_base, a.n);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const u32x4 *A = a.fwd + fwd_off(l) / 8;
+        uint16_t *ht = a.ht + ht_row(l + 1) * a.stride;
+#pragma unroll
+        for (int q = 0; q < kTrainOps; ++q) {
+            const int op = kTrainOps * w + q;
+            u32x4 o[NT];
+            if (l == 0)
+                fwd_pair<2, NT>(A, master + off_b(0), act, op, lane, o);
+            else
+                fwd_pair<8, NT>(A, master + off_b(l), act, op, lane, o);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                store_kblock(ht, a.stride, o[nt], op, lane, s_base + 16 * nt, a.n);
+                xb[l & 1][op][nt][lane] = o[nt];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) act[kb][nt] = xb[l & 1][kb][nt][lane];
+    }
+    if (w != 0) return;
 
     // head: one block of 16 outputs, rows 0 and 1 are z0, z1
     f32x4 acc5[NT];
@@ -295,44 +335,32 @@ __device__ __forceinline__ void mlp_forward_body(const FwdArgs &a) {
         for (int nt = 0; nt < NT; ++nt) acc5[nt] = mfma16(av, act[kb][nt], acc5[nt]);
     }
     const float b50 = master[off_b(4)], b51 = master[off_b(4) + 1];
+    const float inv_n = 1.0f / (float)a.n;
     float lsum = 0.f;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-        const int64_t s = s_base + nt * 16 + col;
+        const int64_t s = s_base + 16 * nt + col;
         const bool valid = s < a.n;
         const float z0 = acc5[nt][0] + b50, z1 = acc5[nt][1] + b51;
         const float V = 1.0f / (1.0f + expf(-z0));
         const float U = z1;   // predicted |T - V|, linear (no saturating activation)
-        if (kMode != kModeTrain) {
-            if (g == 0 && valid) {
-                a.vis[s] = V;
-                if (a.unc) a.unc[s] = U;
-                if (kMode == kModeGrid && a.fb_flag) a.fb_flag[s] = U > a.tau ? 1 : 0;
-            }
-        } else {
-            const float T = Tv[nt];
-            const float e = fabsf(T - V);
-            const float inv_n = 1.0f / (float)a.n;
-            const float dz0 = (V - T) * inv_n;
-            // squared error of U against |T - V| (V held constant)
-            const float dz1 = 2.0f * (U - e) * inv_n;
-            if (g == 0) {
-                a.dz5[s] = valid ? (uint16_t)bf16_bits(dz0) : (uint16_t)0;
-                a.dz5[a.stride + s] = valid ? (uint16_t)bf16_bits(dz1) : (uint16_t)0;
-                if (valid) {
-                    const float bce = -(T * logf(fmaxf(V, 1e-12f)) + (1.f - T) * logf(fmaxf(1.f - V, 1e-12f)));
-                    lsum += bce + (U - e) * (U - e);
-                }
+        const float T = Tv[nt];
+        const float e = fabsf(T - V);
+        const float dz0 = (V - T) * inv_n;
+        // squared error of U against |T - V| (V held constant)
+        const float dz1 = 2.0f * (U - e) * inv_n;
+        if (g == 0) {
+            a.dz5[s] = valid ? (uint16_t)bf16_bits(dz0) : (uint16_t)0;
+            a.dz5[a.stride + s] = valid ? (uint16_t)bf16_bits(dz1) : (uint16_t)0;
+            if (valid) {
+                const float bce = -(T * logf(fmaxf(V, 1e-12f)) + (1.f - T) * logf(fmaxf(1.f - V, 1e-12f)));
+                lsum += bce + (U - e) * (U - e);
             }
         }
     }
-    if (kMode == kModeTrain) {
-        for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
-        if (lane == 0) a.loss_part[wave] = lsum;
-    }
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+    if (lane == 0) a.loss_part[tile] = lsum;
 }
-
-__global__ __launch_bounds__(256, 2) void k_mlp_forward_train(FwdArgs a) { mlp_forward_body<kModeTrain>(a); }
 
 // ---- inference with the weights staged through LDS ------------------------------
 //
@@ -504,45 +532,56 @@ __global__ __launch_bounds__(kInferWaves * 64, 1) void k_mlp_forward(FwdArgs a) 
 
 // ---- backward through the layers ----------------------------------------------
 
-// dH = W dZ for one layer (A = its backward operands, KB k-blocks of the
-// output gradient), then the ReLU mask of the layer's input (feature-major
-// rows ht_in) gives the pre-activation gradient of the layer below, stored
-// feature-major (dz_out) and kept as B operands in act.
-template <int KB>
-__device__ __forceinline__ void dgrad_layer(const u32x4 *__restrict__ A, const uint16_t *__restrict__ ht_in,
-                                            uint16_t *__restrict__ dz_out, int64_t stride, u32x4 (&act)[8][2],
-                                            int lane, int64_t s_base, int64_t n) {
-    f32x4 acc[16][2];
+// Output blocks 2 op and 2 op + 1 of dH = W dZ for NT 16-sample tiles (A =
+// the layer's backward operands, KB k-blocks of the output gradient in act),
+// masked by the ReLU of the layer's input (feature-major rows ht_in): the
+// pre-activation gradient of the layer below, stored as feature-major rows of
+// dz_out and returned as k-block op of the next product's B operand.
+template <int KB, int NT>
+__device__ __forceinline__ void bwd_pair(const u32x4 *__restrict__ A, const uint16_t *__restrict__ ht_in,
+                                         uint16_t *__restrict__ dz_out, int64_t stride, const u32x4 (&act)[8][NT],
+                                         int op, int lane, int64_t s_base, u32x4 (&out)[NT]) {
+    const int g = lane >> 4, col = lane & 15;
+    const bool odd = col & 1;
+    f32x4 acc[2][NT];
 #pragma unroll
-    for (int mb = 0; mb < 16; ++mb)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) acc[mb][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < NT; ++nt) acc[h][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
+        const u32x4 a0 = A[((2 * op) * KB + kb) * 64 + lane];
+        const u32x4 a1 = A[((2 * op + 1) * KB + kb) * 64 + lane];
 #pragma unroll
-        for (int mb = 0; mb < 16; ++mb) {
-            const u32x4 av = A[(mb * KB + kb) * 64 + lane];
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) acc[mb][nt] = mfma16(av, act[kb][nt], acc[mb][nt]);
+        for (int nt = 0; nt < NT; ++nt) {
+            acc[0][nt] = mfma16(a0, act[kb][nt], acc[0][nt]);
+            acc[1][nt] = mfma16(a1, act[kb][nt], acc[1][nt]);
         }
     }
-    const int g = lane >> 4, col = lane & 15;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        const int64_t s = s_base + nt * 16 + col;
-        const bool valid = s < n;
+    for (int h = 0; h < 2; ++h) {
+        // rows mb 16 + 4 g + r of this lane's sample; the pair's loads and
+        // stores cover rows r = 0, 2 (even lane) and 1, 3 (odd lane)
+        const int64_t f0 = (2 * op + h) * 16 + 4 * g + (odd ? 1 : 0);
 #pragma unroll
-        for (int mb = 0; mb < 16; ++mb) {
-            float z[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t f = mb * 16 + 4 * g + r;
-                const bool on = valid && ht_in[f * stride + s] != 0;   // bf16 ReLU output > 0
-                z[r] = on ? acc[mb][nt][r] : 0.0f;
-                dz_out[f * stride + s] = (uint16_t)bf16_bits(z[r]);
-            }
-            act[mb >> 1][nt][(mb & 1) * 2 + 0] = pack2(z[0], z[1]);
-            act[mb >> 1][nt][(mb & 1) * 2 + 1] = pack2(z[2], z[3]);
+        for (int nt = 0; nt < NT; ++nt) {
+            const int64_t s2 = s_base + 16 * nt + (col & ~1);   // first sample of the lane pair
+            // the pair's words of rows (0 | 1) and (2 | 3), both samples; the
+            // same exchange turns them into rows 0 (low) and 1 (high), and 2
+            // and 3, of this lane's own sample
+            const uint32_t r01 = pair_row_word(*reinterpret_cast<const uint32_t *>(ht_in + f0 * stride + s2), odd);
+            const uint32_t r23 =
+                pair_row_word(*reinterpret_cast<const uint32_t *>(ht_in + (f0 + 2) * stride + s2), odd);
+            // the ReLU mask of the layer input (bf16 output > 0; padded samples are 0)
+            const float z0 = (r01 & 0xffffu) != 0u ? acc[h][nt][0] : 0.0f;
+            const float z1 = (r01 >> 16) != 0u ? acc[h][nt][1] : 0.0f;
+            const float z2 = (r23 & 0xffffu) != 0u ? acc[h][nt][2] : 0.0f;
+            const float z3 = (r23 >> 16) != 0u ? acc[h][nt][3] : 0.0f;
+            const uint32_t p01 = pack2(z0, z1), p23 = pack2(z2, z3);
+            out[nt][2 * h + 0] = p01;
+            out[nt][2 * h + 1] = p23;
+            *reinterpret_cast<uint32_t *>(dz_out + f0 * stride + s2) = pair_row_word(p01, odd);
+            *reinterpret_cast<uint32_t *>(dz_out + (f0 + 2) * stride + s2) = pair_row_word(p23, odd);
         }
     }
 }
@@ -555,159 +594,231 @@ struct BwdArgs {
     int64_t n;
 };
 
-__global__ __launch_bounds__(256) void k_mlp_backward(BwdArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t s_base = wave * 32;
-    if (s_base >= a.n) return;
+// Backward through the layers, split as the training forward: one block of
+// kTrainWaves waves per kTrainNT 16-sample tiles, wave w producing k-blocks
+// kTrainOps w .. kTrainOps (w + 1) - 1 of each layer's input gradient,
+// exchanged through LDS.
+__global__ __launch_bounds__(kTrainWaves * 64, 16 / kTrainWaves) void k_mlp_backward(BwdArgs a) {
+    constexpr int NT = kTrainNT;
+    __shared__ u32x4 xb[2][8][NT][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t s_base = (int64_t)blockIdx.x * (16 * NT);
+    if (s_base >= train_pad(a.n)) return;  // block-uniform
     const int g = lane >> 4, col = lane & 15;
-    u32x4 act[8][2];
+    u32x4 act[8][NT];
     // head gradient as a B operand: outputs 0 and 1 sit in slots 0, 1 of lane group 0
     const uint16_t *dz5 = a.dz + dz_row(4) * a.stride;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        const int64_t s = s_base + nt * 16 + col;
+    for (int nt = 0; nt < NT; ++nt) {
+        const int64_t s = s_base + 16 * nt + col;
         act[0][nt] = u32x4{0u, 0u, 0u, 0u};
         if (g == 0) act[0][nt][0] = (uint32_t)dz5[s] | ((uint32_t)dz5[a.stride + s] << 16);
     }
-    dgrad_layer<1>(a.bwd + bwd_off(0) / 8, a.ht + ht_row(4) * a.stride, a.dz + dz_row(3) * a.stride, a.stride, act,
-                   lane, s_base, a.n);
-    dgrad_layer<8>(a.bwd + bwd_off(1) / 8, a.ht + ht_row(3) * a.stride, a.dz + dz_row(2) * a.stride, a.stride, act,
-                   lane, s_base, a.n);
-    dgrad_layer<8>(a.bwd + bwd_off(2) / 8, a.ht + ht_row(2) * a.stride, a.dz + dz_row(1) * a.stride, a.stride, act,
-                   lane, s_base, a.n);
-    dgrad_layer<8>(a.bwd + bwd_off(3) / 8, a.ht + ht_row(1) * a.stride, a.dz + dz_row(0) * a.stride, a.stride, act,
-                   lane, s_base, a.n);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        // j = 0: through W5 (input rows h4, gradient dZ4); j = 3: through W2 (h1, dZ1)
+        const u32x4 *A = a.bwd + bwd_off(j) / 8;
+        const uint16_t *ht_in = a.ht + ht_row(4 - j) * a.stride;
+        uint16_t *dz_out = a.dz + dz_row(3 - j) * a.stride;
+#pragma unroll
+        for (int q = 0; q < kTrainOps; ++q) {
+            const int op = kTrainOps * w + q;
+            u32x4 o[NT];
+            if (j == 0)
+                bwd_pair<1, NT>(A, ht_in, dz_out, a.stride, act, op, lane, s_base, o);
+            else
+                bwd_pair<8, NT>(A, ht_in, dz_out, a.stride, act, op, lane, s_base, o);
+            if (j < 3) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) xb[j & 1][op][nt][lane] = o[nt];
+            }
+        }
+        if (j == 3) break;
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) act[kb][nt] = xb[j & 1][kb][nt][lane];
+    }
 }
 
 // ---- weight gradients ----------------------------------------------------------------
 
-// One wave: a 64 x 64 tile of dW_l[k][o] = sum_s h[k][s] dz[o][s] over one
-// slice of the batch (C[k][o] += A[k x 32 samples] B[32 samples x o]), plus the
-// bias gradient of its 64 outputs when it holds the first k-tile.
+// One block of four waves: a 128 x 128 tile of dW_l[k][o] = sum_s h[k][s]
+// dz[o][s] over one slice of the batch, wave w holding the 64 x 64 quarter
+// (k half w / 2, o half w % 2) as C[k][o] += A[k x 32 samples] B[32 samples x
+// o], plus the bias gradient of its 64 outputs when it holds the layer's
+// first 64 rows. Each 32-sample step stages the tile's 128 h rows and 128 dz
+// rows (64 bytes each) in LDS once for the four waves (double-buffered, one
+// barrier per step); rows are padded to 80 bytes so that a fragment read
+// (16 rows x 16 bytes per lane group) hits 16 distinct bank quadruples.
 struct WgradArgs {
     const uint16_t *ht, *dz;
     int64_t stride;
-    int64_t n_pad;       // samples rounded up to 32
+    int64_t n_pad;       // samples covered (a multiple of 32)
     int64_t slice_len;   // multiple of 32
     int n_slices;
     float *partial;      // [n_slices][n_params]
 };
 
-// tiles per layer: l0: 1 x 4, l1-3: 4 x 4, l4: 4 x 1 -> 56
+// tiles per slice: l0 (64 x 256): 1 x 2, l1-3 (256 x 256): 2 x 2, l4 (256 x 2): 2 x 1 -> 16
 __device__ __forceinline__ void tile_of(int t, int &l, int &kt, int &ot) {
-    if (t < 4) { l = 0; kt = 0; ot = t; return; }
-    t -= 4;
-    if (t < 48) { l = 1 + t / 16; kt = (t % 16) / 4; ot = t % 4; return; }
-    t -= 48;
+    if (t < 2) { l = 0; kt = 0; ot = t; return; }
+    t -= 2;
+    if (t < 12) { l = 1 + t / 4; kt = (t % 4) / 2; ot = t % 2; return; }
+    t -= 12;
     l = 4; kt = t; ot = 0;
 }
-constexpr int kTiles = 56;
+constexpr int kTiles = 16;
+constexpr int kWgRow = 40;   // LDS row stride in bf16 elements (80 bytes: 32 samples + padding)
 
 __global__ __launch_bounds__(256) void k_mlp_wgrad(WgradArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wave >= (int64_t)kTiles * a.n_slices) return;
-    const int tile = (int)(wave % kTiles);
-    const int slice = (int)(wave / kTiles);
+    __shared__ __align__(16) uint16_t hs[2][128 * kWgRow];
+    __shared__ __align__(16) uint16_t ds[2][128 * kWgRow];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tile = (int)(blockIdx.x % kTiles);
+    const int slice = (int)(blockIdx.x / kTiles);
     int l, kt, ot;
     tile_of(tile, l, kt, ot);
-    const int Nout = n_out(l);
-    const int g = lane >> 4, col = lane & 15;
+    const int Nin = n_in(l), Nout = n_out(l);
+    const int k0 = kt * 128, o0 = ot * 128;
     const uint16_t *H = a.ht + ht_row(l) * a.stride;
     const uint16_t *D = a.dz + dz_row(l) * a.stride;
     const int64_t s0 = (int64_t)slice * a.slice_len;
     const int64_t s1 = min(a.n_pad, s0 + a.slice_len);
+    // staging: thread t moves 16-byte part t % 4 of rows t / 4 and 64 + t / 4,
+    // of h and of dz (rows past the layer's inputs or outputs as zeros). A
+    // step's rows are fetched into registers two steps before they are written
+    // to LDS, so each fetch has two steps of products to arrive.
+    const int srow = threadIdx.x >> 2, spart = threadIdx.x & 3;
+    auto fetch = [&](int64_t s, u32x4 (&r)[4]) {
+        if (s >= s1) return;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int row = srow + 64 * u;
+            r[2 * u] = k0 + row < Nin ? *reinterpret_cast<const u32x4 *>(H + (int64_t)(k0 + row) * a.stride + s + 8 * spart)
+                                      : u32x4{0u, 0u, 0u, 0u};
+            r[2 * u + 1] = o0 + row < Nout
+                               ? *reinterpret_cast<const u32x4 *>(D + (int64_t)(o0 + row) * a.stride + s + 8 * spart)
+                               : u32x4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto put = [&](const u32x4 (&r)[4], int buf) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int row = srow + 64 * u;
+            *reinterpret_cast<u32x4 *>(&hs[buf][row * kWgRow + 8 * spart]) = r[2 * u];
+            *reinterpret_cast<u32x4 *>(&ds[buf][row * kWgRow + 8 * spart]) = r[2 * u + 1];
+        }
+    };
+    const int wk = w >> 1, wo = w & 1;
+    // a wave whose quarter lies past the layer's inputs or outputs only stages
+    const bool live = k0 + 64 * wk < Nin && o0 + 64 * wo < Nout;
+    const bool bias = live && k0 + 64 * wk == 0;
+    const int g = lane >> 4, col = lane & 15;
     f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t s = s0; s < s1; s += 32) {
+    // products of the 32 samples staged in buffer buf
+    auto step = [&](int buf) {
+        if (!live) return;
         u32x4 av[4], bv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t k = (int64_t)kt * 64 + i * 16 + col;
-            av[i] = *reinterpret_cast<const u32x4 *>(H + k * a.stride + s + 8 * g);
-        }
+        for (int i = 0; i < 4; ++i)
+            av[i] = *reinterpret_cast<const u32x4 *>(&hs[buf][(64 * wk + 16 * i + col) * kWgRow + 8 * g]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int o = ot * 64 + j * 16 + col;
-            if (o < Nout) {
-                bv[j] = *reinterpret_cast<const u32x4 *>(D + (int64_t)o * a.stride + s + 8 * g);
-            } else {
-                bv[j] = u32x4{0u, 0u, 0u, 0u};
-            }
-            if (kt == 0) {
+        for (int j = 0; j < 4; ++j)
+            bv[j] = *reinterpret_cast<const u32x4 *>(&ds[buf][(64 * wo + 16 * j + col) * kWgRow + 8 * g]);
+        if (bias) {
 #pragma unroll
-                for (int w = 0; w < 4; ++w)
-                    bsum[j] += bf16_val(bv[j][w] & 0xffffu) + bf16_val(bv[j][w] >> 16);
-            }
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bsum[j] += bf16_val(bv[j][q] & 0xffffu) + bf16_val(bv[j][q] >> 16);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+    };
+    u32x4 ra[4], rb[4];
+    fetch(s0, ra);
+    fetch(s0 + 32, rb);
+    put(ra, 0);
+    fetch(s0 + 64, ra);
+    __syncthreads();
+    // two steps per pass: buffer 0 holds step s, registers rb step s + 32 and
+    // ra step s + 64
+    for (int64_t s = s0; s < s1; s += 64) {
+        step(0);
+        if (s + 32 < s1) put(rb, 1);
+        fetch(s + 96, rb);
+        __syncthreads();
+        if (s + 32 >= s1) break;
+        step(1);
+        if (s + 64 < s1) put(ra, 0);
+        fetch(s + 128, ra);
+        __syncthreads();
     }
+    if (!live) return;
     float *P = a.partial + (int64_t)slice * kNParams;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int o = ot * 64 + j * 16 + col;
+            const int o = o0 + 64 * wo + j * 16 + col;
             if (o < Nout) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int k = kt * 64 + i * 16 + 4 * g + r;
+                    const int k = k0 + 64 * wk + i * 16 + 4 * g + r;
                     P[off_w(l) + (int64_t)k * Nout + o] = acc[i][j][r];
                 }
             }
         }
-    if (kt == 0) {
+    if (bias) {
         // lanes col, col+16, col+32, col+48 hold the same output: add the four groups in a fixed order
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             float v = bsum[j];
             const float v1 = __shfl(v, col + 16), v2 = __shfl(v, col + 32), v3 = __shfl(v, col + 48);
             const float v0 = __shfl(v, col);
-            const int o = ot * 64 + j * 16 + col;
+            const int o = o0 + 64 * wo + j * 16 + col;
             if (g == 0 && o < Nout) P[off_b(l) + o] = ((v0 + v1) + v2) + v3;
         }
     }
 }
 
-// grad[p] = sum over slices (in order) of partial[slice][p]; loss = sum of wave partials / n
+// grad[p] = sum over slices (in order) of partial[slice][p], eight loads in
+// flight per thread; loss = sum of the wave partials / n, by the first wave of
+// block 0 (lane l takes partials l, l + 64, ..., then a fixed butterfly).
 __global__ __launch_bounds__(256) void k_reduce_grad(const float *__restrict__ partial, int n_slices,
                                                      float *__restrict__ grad, const float *__restrict__ loss_part,
                                                      int64_t n_waves, int64_t n, float *__restrict__ loss_out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < kNParams) {
         float s = 0.f;
-        for (int i = 0; i < n_slices; ++i) s += partial[(int64_t)i * kNParams + p];
+        int i = 0;
+        for (; i + 8 <= n_slices; i += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(i + u) * kNParams + p];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; i < n_slices; ++i) s += partial[(int64_t)i * kNParams + p];
         grad[p] = s;
     }
-    if (p == 0 && loss_out) {
+    if (blockIdx.x == 0 && threadIdx.x < 64 && loss_out) {
         double s = 0.0;
-        for (int64_t w = 0; w < n_waves; ++w) s += loss_part[w];
-        *loss_out = (float)(s / (double)n);
+        for (int64_t w = threadIdx.x; w < n_waves; w += 64) s += loss_part[w];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (threadIdx.x == 0) *loss_out = (float)(s / (double)n);
     }
 }
 
 // ---- optimiser and packing ---------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                                              const float *__restrict__ grad, float lr, float beta1, float beta2,
-                                              float eps, float c1, float c2) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= kNParams) return;
-    const float gr = grad[p];
-    const float mm = beta1 * m[p] + (1.f - beta1) * gr;
-    const float vv = beta2 * v[p] + (1.f - beta2) * gr * gr;
-    m[p] = mm;
-    v[p] = vv;
-    w[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
-}
 
 // BF16 A operands from the FP32 master weights (see kfeat).
 __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ master, uint16_t *__restrict__ fwd,
@@ -737,6 +848,70 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ master, 
         const int k = mb * 16 + (lane & 15), o = kfeat(kb, lane >> 4, s);
         const float w = (o < n_out(l)) ? master[off_w(l) + (int64_t)k * n_out(l) + o] : 0.0f;
         bwd[eb] = (uint16_t)bf16_bits(w);
+    }
+}
+
+// Positions of weight W_l[k][o] (l = 0..4) in the packed operands: its
+// forward A-operand element, and for l >= 1 its backward A-operand element
+// (the inverse of the element -> weight map of k_pack).
+__device__ __forceinline__ int64_t fwd_pos(int l, int k, int o) {
+    const int KB = n_in(l) / 32;
+    const int kb = k >> 5, g = (k & 15) >> 2, sl = ((k & 31) >> 4) * 4 + (k & 3);
+    const int64_t blk = (int64_t)(o >> 4) * KB + kb;
+    return fwd_off(l) + blk * 512 + (g * 16 + (o & 15)) * 8 + sl;
+}
+__device__ __forceinline__ int64_t bwd_pos(int l, int k, int o) {
+    const int KB = (l == 4) ? 1 : 8;
+    const int kb = o >> 5, g = (o & 15) >> 2, sl = ((o & 31) >> 4) * 4 + (o & 3);
+    const int64_t blk = (int64_t)(k >> 4) * KB + kb;
+    return bwd_off(4 - l) + blk * 512 + (g * 16 + (k & 15)) * 8 + sl;
+}
+
+// One training step's update, fused per parameter: the gradient as the
+// in-order sum of the slice partials (as k_reduce_grad), the Adam update with
+// bias-corrected moments (c1 = 1 - beta1^t, c2 = 1 - beta2^t), and the bf16
+// copies of a weight in the packed operands (as k_pack; the padding elements
+// stay the zeros written at initialisation). The loss is summed as in
+// k_reduce_grad.
+__global__ __launch_bounds__(256) void k_adam_pack(const float *__restrict__ partial, int n_slices,
+                                                   float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                                   uint16_t *__restrict__ fwd, uint16_t *__restrict__ bwd, float lr,
+                                                   float beta1, float beta2, float eps, float c1, float c2,
+                                                   const float *__restrict__ loss_part, int64_t n_waves, int64_t n,
+                                                   float *__restrict__ loss_out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kNParams) {
+        float gr = 0.f;
+        int i = 0;
+        for (; i + 8 <= n_slices; i += 8) {
+            float vs[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vs[u] = partial[(int64_t)(i + u) * kNParams + p];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) gr += vs[u];
+        }
+        for (; i < n_slices; ++i) gr += partial[(int64_t)i * kNParams + p];
+        const float mm = beta1 * m[p] + (1.f - beta1) * gr;
+        const float vv = beta2 * v[p] + (1.f - beta2) * gr * gr;
+        m[p] = mm;
+        v[p] = vv;
+        const float wn = w[p] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+        w[p] = wn;
+        int l = 0;
+        while (l < 4 && p >= off_w(l + 1)) ++l;
+        const int64_t r = p - off_w(l);
+        if (r < (int64_t)n_in(l) * n_out(l)) {   // a weight (the layer's biases follow its weights)
+            const int k = (int)(r / n_out(l)), o = (int)(r - (int64_t)k * n_out(l));
+            const uint16_t b = (uint16_t)bf16_bits(wn);
+            fwd[fwd_pos(l, k, o)] = b;
+            if (l >= 1) bwd[bwd_pos(l, k, o)] = b;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 64 && loss_out) {
+        double s = 0.0;
+        for (int64_t q = threadIdx.x; q < n_waves; q += 64) s += loss_part[q];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (threadIdx.x == 0) *loss_out = (float)(s / (double)n);
     }
 }
 
@@ -867,7 +1042,7 @@ __global__ __launch_bounds__(256) void k_ray_setup(const float *__restrict__ mea
 constexpr int64_t kSliceLen = 1024;
 
 struct TrainWs {
-    size_t ht, dz, partial, grad, loss_part, loss, total;
+    size_t ht, dz, partial, loss_part, loss, total;
     int64_t stride, n_slices, n_waves;
 };
 
@@ -876,12 +1051,11 @@ inline TrainWs train_ws(int64_t batch) {
     const int64_t pad = ((batch + 127) / 128) * 128;
     W.stride = pad;
     W.n_slices = (pad + kSliceLen - 1) / kSliceLen;
-    W.n_waves = pad / 32;
+    W.n_waves = train_pad(batch) / (16 * kTrainNT);   // one loss partial per training block
     size_t off = 0;
     W.ht = off; off = align_up(off + (size_t)kHtRows * pad * 2);
     W.dz = off; off = align_up(off + (size_t)kDzRows * pad * 2);
     W.partial = off; off = align_up(off + (size_t)W.n_slices * kNParams * 4);
-    W.grad = off; off = align_up(off + (size_t)kNParams * 4);
     W.loss_part = off; off = align_up(off + (size_t)W.n_waves * 4);
     W.loss = off; off = align_up(off + 256);
     W.total = off;
@@ -895,11 +1069,12 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 constexpr int64_t kLaunchSamples = int64_t(1) << 30;
 
 // forward (train) + backward + weight gradients + reduction on samples [0, n)
+// With grad == nullptr the slice partials are left for k_adam_pack.
 rv_status loss_grad_impl(const void *params, const float *x, const float *d, const float *T, int64_t n, bool hashed,
                          int64_t n_samples, uint64_t seed, int64_t step, float *grad, float *loss_out, void *ws,
                          const TrainWs &W, hipStream_t s) {
     const SurLayout L = sur_layout();
-    const int64_t n_pad = ((n + 31) / 32) * 32;
+    const int64_t n_pad = train_pad(n);
     FwdArgs fa{};
     fa.master = at<float>(params, L.master);
     fa.fwd = at<u32x4>(params, L.fwd);
@@ -916,10 +1091,10 @@ rv_status loss_grad_impl(const void *params, const float *x, const float *d, con
     fa.stride = W.stride;
     fa.dz5 = at<uint16_t>(ws, W.dz) + dz_row(4) * W.stride;
     fa.loss_part = at<float>(ws, W.loss_part);
-    const int64_t waves = n_pad / 32;
-    hipLaunchKernelGGL(k_mlp_forward_train, dim3(blocks_for(waves, 4)), dim3(256), 0, s, fa);
+    const int64_t tiles = n_pad / (16 * kTrainNT);   // one block per kTrainNT 16-sample tiles
+    hipLaunchKernelGGL(k_mlp_forward_train, dim3((unsigned)tiles), dim3(kTrainWaves * 64), 0, s, fa);
     BwdArgs ba{at<u32x4>(params, L.bwd), at<uint16_t>(ws, W.ht), at<uint16_t>(ws, W.dz), W.stride, n};
-    hipLaunchKernelGGL(k_mlp_backward, dim3(blocks_for(waves, 4)), dim3(256), 0, s, ba);
+    hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)tiles), dim3(kTrainWaves * 64), 0, s, ba);
     WgradArgs wa{};
     wa.ht = at<uint16_t>(ws, W.ht);
     wa.dz = at<uint16_t>(ws, W.dz);
@@ -928,9 +1103,10 @@ rv_status loss_grad_impl(const void *params, const float *x, const float *d, con
     wa.slice_len = kSliceLen;
     wa.n_slices = (int)((n_pad + kSliceLen - 1) / kSliceLen);
     wa.partial = at<float>(ws, W.partial);
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(blocks_for((int64_t)kTiles * wa.n_slices, 4)), dim3(256), 0, s, wa);
-    hipLaunchKernelGGL(k_reduce_grad, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, wa.partial, wa.n_slices, grad,
-                       at<float>(ws, W.loss_part), waves, n, loss_out);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)(kTiles * wa.n_slices)), dim3(256), 0, s, wa);
+    if (grad)
+        hipLaunchKernelGGL(k_reduce_grad, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, wa.partial, wa.n_slices,
+                           grad, at<float>(ws, W.loss_part), tiles, n, loss_out);
     return check_launch("surrogate loss/gradient");
 }
 
@@ -1019,11 +1195,13 @@ extern "C" rv_status rv_surrogate_train(void *params, const float *x, const floa
     RV_REQUIRE(ws_bytes >= W.total, RV_ERR_WORKSPACE, "rv_surrogate_train: ws_bytes %zu < %zu", ws_bytes, W.total);
     const SurLayout L = sur_layout();
     hipStream_t s = (hipStream_t)stream;
-    float *grad = at<float>(ws, W.grad);
+    const int64_t n_pad = train_pad(o->batch);
+    const int n_slices = (int)((n_pad + kSliceLen - 1) / kSliceLen);
+    const int64_t n_parts = n_pad / (16 * kTrainNT);
     for (int64_t it = 0; it < o->steps; ++it) {
         const int64_t gstep = o->step0 + it;
-        rv_status st = loss_grad_impl(params, x, d, T, o->batch, true, n_samples, o->seed, gstep, grad,
-                                      loss_log ? loss_log + it : nullptr, ws, W, s);
+        rv_status st = loss_grad_impl(params, x, d, T, o->batch, true, n_samples, o->seed, gstep, nullptr, nullptr,
+                                      ws, W, s);
         if (st != RV_OK) return st;
         // cosine-decayed step size and bias corrections (host arithmetic, FP64)
         double lr = o->lr;
@@ -1034,11 +1212,11 @@ extern "C" rv_status rv_surrogate_train(void *params, const float *x, const floa
         const double tt = (double)(gstep + 1);
         const float c1 = (float)(1.0 - std::pow((double)o->beta1, tt));
         const float c2 = (float)(1.0 - std::pow((double)o->beta2, tt));
-        hipLaunchKernelGGL(k_adam, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, at<float>(params, L.master),
-                           at<float>(params, L.m), at<float>(params, L.v), (const float *)grad, (float)lr, o->beta1,
-                           o->beta2, o->eps, c1, c2);
-        hipLaunchKernelGGL(k_pack, dim3(blocks_for(kFwdTotal + kBwdTotal, 256)), dim3(256), 0, s,
-                           at<float>(params, L.master), at<uint16_t>(params, L.fwd), at<uint16_t>(params, L.bwd));
+        hipLaunchKernelGGL(k_adam_pack, dim3(blocks_for(kNParams, 256)), dim3(256), 0, s, at<float>(ws, W.partial),
+                           n_slices, at<float>(params, L.master), at<float>(params, L.m), at<float>(params, L.v),
+                           at<uint16_t>(params, L.fwd), at<uint16_t>(params, L.bwd), (float)lr, o->beta1, o->beta2,
+                           o->eps, c1, c2, at<float>(ws, W.loss_part), n_parts, (int64_t)o->batch,
+                           loss_log ? loss_log + it : nullptr);
         st = check_launch("rv_surrogate_train");
         if (st != RV_OK) return st;
     }
