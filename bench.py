@@ -100,9 +100,10 @@ def parse():
     ap.add_argument("--no-shade", action="store_true", help="skip the PBR shading leg")
     ap.add_argument("--no-sh", action="store_true", help="skip the SH-compressed visibility leg")
     ap.add_argument("--sur-train-samples", type=int, default=50_000_000)
-    ap.add_argument("--sur-steps", type=int, default=24416,
-                    help="optimiser steps (24416 x 16384 = eight passes over 50M; the fallback needed for MAE 0.02 "
-                         "falls with the number of steps: 63 %% after two passes, 54 %% after four, 52 %% after six)")
+    ap.add_argument("--sur-steps", type=int, default=73248,
+                    help="optimiser steps (73248 x 16384 = 24 passes over 50M; the fallback needed for MAE 0.02 "
+                         "falls with the number of steps: 63 %% after two passes, 54 %% after four, 50 %% after "
+                         "eight, 48 %% after 16)")
     ap.add_argument("--sur-batch", type=int, default=16384)
     ap.add_argument("--sur-mae", type=float, default=0.02, help="target mean absolute visibility error")
     return ap.parse_args()
