@@ -76,6 +76,16 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
 }
 __device__ __forceinline__ float bf16_val(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 
+// ReLU of two bf16 values in one word: read as 16-bit integers, a bf16 value
+// is negative exactly when its sign bit is set, so the per-half integer max
+// with 0 is the ReLU (-0 becomes +0). Rounding to bf16 preserves sign and
+// zero, so this equals rounding the ReLU of the FP32 values.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t w) {
+    typedef short i16x2 __attribute__((ext_vector_type(2)));
+    const i16x2 z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16x2, w), z));
+}
+
 // Feature carried by slot s (0..7) of lane group g (lane / 16) in k-block kb of
 // a B operand built from accumulators: blocks 2kb and 2kb+1 of 16 outputs,
 // four consecutive outputs per lane group.
@@ -153,7 +163,8 @@ __host__ __device__ constexpr int64_t dz_row(int l) { return l < 4 ? (int64_t)l 
 
 // Output blocks 2 op and 2 op + 1 of a hidden layer for NT 16-sample tiles:
 // act (B operands, k-blocks of the input) -> the ReLU outputs as k-block op of
-// the next layer's B operand (bias, ReLU, one v_cvt_pk_bf16_f32 per pair).
+// the next layer's B operand (bias in FP32, one v_cvt_pk_bf16_f32 per pair, then the ReLU
+// on the packed word).
 template <int KB, int NT>
 __device__ __forceinline__ void fwd_pair(const u32x4 *__restrict__ A, const float *__restrict__ bias,
                                          const u32x4 (&act)[8][NT], int op, int lane, u32x4 (&out)[NT]) {
@@ -178,8 +189,8 @@ __device__ __forceinline__ void fwd_pair(const u32x4 *__restrict__ A, const floa
         const float4 bv = *reinterpret_cast<const float4 *>(bias + (2 * op + h) * 16 + 4 * g);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            out[nt][2 * h + 0] = pack2(fmaxf(acc[h][nt][0] + bv.x, 0.f), fmaxf(acc[h][nt][1] + bv.y, 0.f));
-            out[nt][2 * h + 1] = pack2(fmaxf(acc[h][nt][2] + bv.z, 0.f), fmaxf(acc[h][nt][3] + bv.w, 0.f));
+            out[nt][2 * h + 0] = relu_bf16x2(pack2(acc[h][nt][0] + bv.x, acc[h][nt][1] + bv.y));
+            out[nt][2 * h + 1] = relu_bf16x2(pack2(acc[h][nt][2] + bv.z, acc[h][nt][3] + bv.w));
         }
     }
 }
@@ -400,6 +411,7 @@ __device__ __forceinline__ void chunk_barrier() {
 
 // Output pair OP0 + o of a layer (the same arithmetic as hidden_layer) from
 // the LDS chunk holding the A operands of pairs OP0, OP0 + 1, ...
+
 template <int KB, int NT, int OP0>
 __device__ __forceinline__ void layer_ops_lds_one(const u32x4 *A, int o, const float *__restrict__ bias,
                                                   const u32x4 (&act)[8][NT], u32x4 (&out)[8][NT], int lane) {
@@ -422,15 +434,14 @@ __device__ __forceinline__ void layer_ops_lds_one(const u32x4 *A, int o, const f
         __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 2 * NT, 0);
     }
+    // bias in FP32, then the bf16 pair, then the ReLU on the packed words
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const float4 bv = *reinterpret_cast<const float4 *>(bias + (2 * (OP0 + o) + h) * 16 + 4 * g);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const float h0 = fmaxf(acc[h][nt][0] + bv.x, 0.f), h1 = fmaxf(acc[h][nt][1] + bv.y, 0.f);
-            const float h2 = fmaxf(acc[h][nt][2] + bv.z, 0.f), h3 = fmaxf(acc[h][nt][3] + bv.w, 0.f);
-            out[OP0 + o][nt][2 * h + 0] = pack2(h0, h1);
-            out[OP0 + o][nt][2 * h + 1] = pack2(h2, h3);
+            out[OP0 + o][nt][2 * h + 0] = relu_bf16x2(pack2(acc[h][nt][0] + bv.x, acc[h][nt][1] + bv.y));
+            out[OP0 + o][nt][2 * h + 1] = relu_bf16x2(pack2(acc[h][nt][2] + bv.z, acc[h][nt][3] + bv.w));
         }
     }
 }
