@@ -246,12 +246,27 @@ __device__ __forceinline__ void encode_tiles(const FwdArgs &a, int64_t s_base, i
     for (int nt = 0; nt < NT; ++nt) {
         const int64_t s = s_base + nt * 16 + col;
         const bool valid = s < a.n;
+        // grid queries q = i K + k: the tile's first query is split once per
+        // wave (scalar), each lane's is at most 15 further on
+        int64_t gi = 0;
+        int gk = 0;
+        if (kMode == kModeGrid) {
+            const int64_t qt = a.q_begin + s_base + nt * 16;
+            const int64_t q0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(qt >> 32)) << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)qt);
+            const int64_t i0 = q0 / a.K;
+            gi = i0;
+            gk = (int)(q0 - i0 * a.K) + col;
+            while (gk >= a.K) {
+                gk -= a.K;
+                ++gi;
+            }
+        }
         float x0 = 0.f, x1 = 0.f, x2 = 0.f, d0 = 0.f, d1 = 0.f, d2 = 1.f;
         if (valid) {
             if (kMode == kModeGrid) {
-                const int64_t q = a.q_begin + s;
-                const int64_t i = q / a.K;
-                const int k = (int)(q - i * a.K);
+                const int64_t i = gi;
+                const int k = gk;
                 float nx = 0.f, ny = 0.f, nz = 1.f;
                 if (a.gnormal) {
                     nx = a.gnormal[3 * i]; ny = a.gnormal[3 * i + 1]; nz = a.gnormal[3 * i + 2];
@@ -988,6 +1003,7 @@ __global__ __launch_bounds__(256) void k_fallback_rows(const float *__restrict__
     // with a tree built for another Gaussian set the records are not read:
     // Gaussians are taken in index order (the traversal then gives NaN)
     const bool tree_ok = tree_matches(header, n);
+    const bool aligned = K % 16 == 0 && q_begin % 16 == 0;
     for (int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); grp < n_groups; grp += (int64_t)gridDim.x * 4) {
         const int64_t m = grp * 64 + lane;
         // this lane's Gaussian and the directions of it that lie in the range
@@ -1003,12 +1019,42 @@ __global__ __launch_bounds__(256) void k_fallback_rows(const float *__restrict__
         const bool any = __ballot(k_lo < k_hi) != 0;
         if (!any) continue;  // wave-uniform
         int total = 0;
+        unsigned long long base = 0;
+        if (aligned) {
+            // rows start on 16-byte boundaries: 16 flags per lane per load
+            // (the flag buffer is padded to 256 bytes, so a row's last load
+            // stays inside it); two passes, counting then writing
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int k0 = 0; k0 < K; k0 += 16) {
+                    u32x4 w = u32x4{0u, 0u, 0u, 0u};
+                    if (k0 + 16 > k_lo && k0 < k_hi)
+                        w = *reinterpret_cast<const u32x4 *>(flag + row + k0);
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int k = k0 + u;
+                        const bool f = k >= k_lo && k < k_hi && ((w[u >> 2] >> (8 * (u & 3))) & 0xffu) != 0;
+                        const uint64_t b = __ballot(f);
+                        if (pass == 0) {
+                            total += __popcll(b);
+                        } else {
+                            if (f) list[base + __popcll(b & lt)] = row + k;
+                            base += __popcll(b);
+                        }
+                    }
+                }
+                if (pass == 0) {
+                    if (total == 0) break;
+                    if (lane == 0) base = atomicAdd(count, (unsigned long long)total);
+                    base = __shfl(base, 0);
+                }
+            }
+            continue;
+        }
         for (int k = 0; k < K; ++k) {
             const bool f = k >= k_lo && k < k_hi && flag[row + k] != 0;
             total += __popcll(__ballot(f));
         }
         if (total == 0) continue;
-        unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(count, (unsigned long long)total);
         base = __shfl(base, 0);
         for (int k = 0; k < K; ++k) {

@@ -119,14 +119,17 @@ def test_adam_step_matches_oracle():
     assert not off.any() or np.abs(g[off]).max() <= 0.25 * rms
 
 
-def test_grid_inference_with_fallback_matches_tracer():
+# (first query, query count, directions): an unaligned range takes the
+# fallback list's byte-wise path, the aligned ones (K and the first query
+# multiples of 16) its 16-flag loads, the last with a ragged end
+@pytest.mark.parametrize("q0,qn,K", [(1234, 100_001, 32), (0, 100_000, 32), (4096, 65_531, 48)])
+def test_grid_inference_with_fallback_matches_tracer(q0, qn, K):
     sc = scenes.make_object_scene(20_000, 1)
-    dirs = scenes.fibonacci_dirs(32, True)
+    dirs = scenes.fibonacci_dirs(K, True)
     g = Gaussians.from_scene(sc)
     bvh = build_bvh(g)
     net = Surrogate(sc["mean"].min(0), sc["mean"].max(0), seed=5)
     prm = TraceParams()
-    q0, qn = 1234, 100_001
     vis0, unc0, _ = net.infer_grid(g, dirs, prm, q0, qn)
     tau = float(unc0.median())
     vis, unc, nfb = net.infer_grid(g, dirs, prm, q0, qn, tau=tau, bvh=bvh)
