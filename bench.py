@@ -100,11 +100,12 @@ def parse():
     ap.add_argument("--no-shade", action="store_true", help="skip the PBR shading leg")
     ap.add_argument("--no-sh", action="store_true", help="skip the SH-compressed visibility leg")
     ap.add_argument("--sur-train-samples", type=int, default=50_000_000)
-    ap.add_argument("--sur-steps", type=int, default=73248,
-                    help="optimiser steps (73248 x 16384 = 24 passes over 50M; the fallback needed for MAE 0.02 "
-                         "falls with the number of steps: 63 %% after two passes, 54 %% after four, 50 %% after "
-                         "eight, 48 %% after 16)")
-    ap.add_argument("--sur-batch", type=int, default=16384)
+    ap.add_argument("--sur-steps", type=int, default=146496,
+                    help="optimiser steps (146496 x 8192 = 24 passes over 50M; the fallback needed for MAE 0.02 "
+                         "falls with the number of steps: at batches of 16384, 63 %% after two passes, 54 %% after "
+                         "four, 50 %% after eight, 48 %% after 16, 47 %% after 24)")
+    ap.add_argument("--sur-batch", type=int, default=8192)
+    ap.add_argument("--sur-lr", type=float, default=2e-3, help="Adam step size, cosine-decayed to 1/40 of it")
     ap.add_argument("--sur-mae", type=float, default=0.02, help="target mean absolute visibility error")
     return ap.parse_args()
 
@@ -152,7 +153,8 @@ def surrogate_leg(args, torch, g, dirs, prm, bvh, vis_ray, plain_rays_per_s):
     untrained = Surrogate(lo, hi, seed=1, device=dev)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    tlog = net.train(o, d, T_tr, steps=args.sur_steps, batch=args.sur_batch, lr=2e-3, lr_min=5e-5, seed=7)
+    tlog = net.train(o, d, T_tr, steps=args.sur_steps, batch=args.sur_batch, lr=args.sur_lr, lr_min=args.sur_lr / 40,
+                     seed=7)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t
     log(f"surrogate trained: {args.sur_steps} steps of {args.sur_batch} in {train_s:.2f} s, loss "
