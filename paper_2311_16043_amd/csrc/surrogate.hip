@@ -1096,7 +1096,18 @@ __global__ __launch_bounds__(256) void k_ray_setup(const float *__restrict__ mea
 
 // ---- training workspace --------------------------------------------------------------------------------
 
-constexpr int64_t kSliceLen = 1024;
+// The weight gradients are summed over at most kMaxSlices slices of the
+// batch (a multiple of 32 samples each), so that the 16 tiles of every slice
+// give 256 blocks whatever the batch; the slice partials are added in order.
+constexpr int kMaxSlices = 16;
+inline int64_t slice_len_for(int64_t n_pad) {
+    const int64_t per = (n_pad + kMaxSlices - 1) / kMaxSlices;
+    return std::max<int64_t>(32, ((per + 31) / 32) * 32);
+}
+inline int slices_for(int64_t n_pad) {
+    const int64_t len = slice_len_for(n_pad);
+    return (int)((n_pad + len - 1) / len);
+}
 
 struct TrainWs {
     size_t ht, dz, partial, loss_part, loss, total;
@@ -1107,7 +1118,7 @@ inline TrainWs train_ws(int64_t batch) {
     TrainWs W{};
     const int64_t pad = ((batch + 127) / 128) * 128;
     W.stride = pad;
-    W.n_slices = (pad + kSliceLen - 1) / kSliceLen;
+    W.n_slices = kMaxSlices;
     W.n_waves = train_pad(batch) / (16 * kTrainNT);   // one loss partial per training block
     size_t off = 0;
     W.ht = off; off = align_up(off + (size_t)kHtRows * pad * 2);
@@ -1157,8 +1168,8 @@ rv_status loss_grad_impl(const void *params, const float *x, const float *d, con
     wa.dz = at<uint16_t>(ws, W.dz);
     wa.stride = W.stride;
     wa.n_pad = n_pad;
-    wa.slice_len = kSliceLen;
-    wa.n_slices = (int)((n_pad + kSliceLen - 1) / kSliceLen);
+    wa.slice_len = slice_len_for(n_pad);
+    wa.n_slices = slices_for(n_pad);
     wa.partial = at<float>(ws, W.partial);
     hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)(kTiles * wa.n_slices)), dim3(256), 0, s, wa);
     if (grad)
@@ -1253,7 +1264,7 @@ extern "C" rv_status rv_surrogate_train(void *params, const float *x, const floa
     const SurLayout L = sur_layout();
     hipStream_t s = (hipStream_t)stream;
     const int64_t n_pad = train_pad(o->batch);
-    const int n_slices = (int)((n_pad + kSliceLen - 1) / kSliceLen);
+    const int n_slices = slices_for(n_pad);
     const int64_t n_parts = n_pad / (16 * kTrainNT);
     for (int64_t it = 0; it < o->steps; ++it) {
         const int64_t gstep = o->step0 + it;
