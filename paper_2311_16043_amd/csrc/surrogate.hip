@@ -300,11 +300,11 @@ __device__ __forceinline__ void encode_tiles(const FwdArgs &a, int64_t s_base, i
 }
 
 // Training forward: one block of kTrainWaves waves per kTrainNT 16-sample
-// tiles. Wave w produces output blocks of k-blocks kTrainOps w .. kTrainOps
-// (w + 1) - 1 of every hidden layer's output (the next layer's input) and
-// stores them as feature-major rows; the waves exchange each layer's output
-// through LDS (double-buffered, one barrier per layer). Wave 0 evaluates the
-// head and the loss.
+// tiles. Of every hidden layer's 16 output blocks (8 k-blocks of the next
+// layer's input), wave w produces k-blocks kTrainOps w .. kTrainOps (w + 1) - 1
+// and stores them as feature-major rows; the waves exchange each layer's
+// output through LDS (double-buffered, one barrier per layer). Wave 0
+// evaluates the head and the loss.
 __global__ __launch_bounds__(kTrainWaves * 64, 16 / kTrainWaves) void k_mlp_forward_train(FwdArgs a) {
     constexpr int NT = kTrainNT;
     __shared__ u32x4 xb[2][8][NT][64];
@@ -998,7 +998,6 @@ __global__ __launch_bounds__(256) void k_fallback_rows(const float *__restrict__
                                                        int64_t *__restrict__ list) {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = (1ull << lane) - 1ull;
-    const int64_t q_end = q_begin + q_count;
     const int64_t n_groups = (n + 63) / 64;
     // with a tree built for another Gaussian set the records are not read:
     // Gaussians are taken in index order (the traversal then gives NaN)
