@@ -8,11 +8,14 @@ of the last product's terms (V through the sigmoid's slope <= 1/4), and the
 outputs' relative Frobenius error <= 1e-3; per layer, the gradient's relative
 Frobenius error <= 4e-3 and its largest element error <= 1e-2 of its largest
 element."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
 
 from oracle import mlp
+from paper_2311_16043_amd import _lib
 from paper_2311_16043_amd import Gaussians, Surrogate, TraceParams, build_bvh, ray_setup, trace_rays, trace_visibility
 from workloads import mlp_init, scenes
 
@@ -21,6 +24,9 @@ from test_oracle_mlp_pins import C_OUT, GRAD_FROB, GRAD_MAXABS, OUT_FROB, layer_
 pytestmark = pytest.mark.gpu
 
 BOX_LO, BOX_HI = np.array([-2.0, -2.0, -0.1]), np.array([2.0, 2.0, 2.1])
+# packed BF16 operands: forward (five layers, the head padded to 16 rows) and
+# backward (W5 .. W2), in elements
+FWD_ELEMS, BWD_ELEMS = 217_088, 204_800
 
 
 def _inputs(n, seed):
@@ -117,6 +123,28 @@ def test_adam_step_matches_oracle():
     # float32/BF16 evaluation of this batch flips on elements up to 0.126 RMS
     # (a ReLU within rounding of zero switches a whole term)
     assert not off.any() or np.abs(g[off]).max() <= 0.25 * rms
+
+
+def _packed_operands(net):
+    """The blob's BF16 forward and backward A operands (contiguous)."""
+    v = _lib.RvSurrogateArrays()
+    _lib.call("rv_surrogate_view", net.blob.data_ptr(), ctypes.byref(v))
+    off = v.packed - net.blob.data_ptr()
+    return net.blob[off:off + 2 * (FWD_ELEMS + BWD_ELEMS)].clone()
+
+
+def test_training_steps_repack_the_bf16_operands():
+    """A training step writes each updated weight's BF16 copies straight into
+    the packed operands; they must equal a fresh packing of the new FP32
+    weights (the initialisation's packing)."""
+    net, _ = _net(17)
+    x, d, T = _inputs(20_000, 5)
+    net.train(torch.from_numpy(x), torch.from_numpy(d), torch.from_numpy(T), steps=3, batch=2048, lr=1e-3, seed=3)
+    ref = Surrogate(BOX_LO, BOX_HI, init_weights=net.master.clone())
+    torch.cuda.synchronize()
+    a, b = _packed_operands(net), _packed_operands(ref)
+    assert not torch.equal(net.master, torch.from_numpy(mlp_init.he_uniform(17)).to(net.master.device))
+    assert torch.equal(a, b), int((a != b).sum())
 
 
 # (first query, query count, directions): an unaligned range takes the
