@@ -226,11 +226,9 @@ __device__ __forceinline__ void store_kblock(uint16_t *__restrict__ ht, int64_t 
     }
 }
 
-// A wave handles NT tiles of 16 samples (two in training, three in
-// inference); several waves share a SIMD, so one wave's vector work overlaps
-// the others' matrix products.
 // The encoded inputs of NT tiles of 16 samples from s_base as B operands
 // (k-blocks 0 and 1 of act; features kfeat), and the targets in training.
+// Every wave of a training block encodes its block's tiles itself.
 template <int kMode, int NT>
 __device__ __forceinline__ void encode_tiles(const FwdArgs &a, int64_t s_base, int lane, u32x4 (&act)[8][NT],
                                              float (&Tv)[NT]) {
