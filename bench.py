@@ -62,11 +62,16 @@ def sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# committed counter profiles of the traversal, per workload
+TRAFFIC_PROFILES = {"object": "profiles/trace_object_scale_counters.md",
+                    "surrogate": "profiles/trace_surrogate_counters.md"}
+
+
 def recorded_traffic(workload: str):
     """HBM bytes per launch of k_trace_stream from the committed counter
     profile of this workload, if it was taken on the kernel sources as they
     are now (else None), with the file it came from."""
-    path = f"profiles/trace_{workload}_counters.md"
+    path = TRAFFIC_PROFILES.get(workload, f"profiles/trace_{workload}_counters.md")
     try:
         text = open(os.path.join(ROOT, path)).read()
     except OSError:

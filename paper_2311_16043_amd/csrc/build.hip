@@ -5,12 +5,17 @@
 // Pipeline on one stream, no host synchronisation:
 //   bounds_partial/bounds_final   min/max of the means (exact in any order)
 //   morton                        63-bit keys in binary32 arithmetic
-//   sort_hist/sort_scan/sort_scatter x 8   stable LSD radix sort, 8-bit digits,
-//                                 wave64 ballot ranking, one wave per tile
+//   sort_hist, scan_seg_sum/sort_scan/scan_seg_apply, sort_scatter  x 8
+//                                 stable LSD radix sort, 8-bit digits, wave64
+//                                 ballot ranking, one wave per tile, two-level
+//                                 prefix sum of the digit counts
 //   leaf_prep                     per sorted leaf: whitening W, 3-sigma box, origin data
 //   karras                        internal nodes and parents, one thread per node
-//   block_boxes + refit_ranges    each child box the union of the leaf boxes of
-//                                 its sorted-leaf range (no ordering between nodes)
+//   block_boxes, refit_lanes + refit_ranges
+//                                 each child box the union of the leaf boxes of
+//                                 its sorted-leaf range (no ordering between
+//                                 nodes): a lane per node for short ranges, a
+//                                 wave per node for the rest
 //   collapse4                     compressed four-wide records the tracer walks
 #include "rv_internal.h"
 
@@ -137,7 +142,65 @@ __global__ __launch_bounds__(kSortWave) void k_sort_hist(const uint64_t *__restr
     for (int i = lane; i < 256; i += kSortWave) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
 }
 
-// Exclusive prefix sum over hist[256 * nblocks] (digit-major) in one block.
+// Exclusive prefix sum of the digit-major counts hist[256 * nblocks] in two
+// levels: k_scan_seg_sum adds each segment of kScanSeg counts, k_sort_scan
+// (one block) turns the segment sums into segment offsets, and
+// k_scan_seg_apply scans each segment from its offset. Integer sums: the
+// result is the plain prefix sum whatever the grouping.
+
+// seg[b] = sum of hist[b kScanSeg, (b + 1) kScanSeg), clipped to total
+// (256 threads, four counts each).
+__global__ __launch_bounds__(256) void k_scan_seg_sum(const uint32_t *__restrict__ hist, int64_t total,
+                                                      uint32_t *__restrict__ seg) {
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanSeg;
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = base + k * 256 + t;
+        if (i < total) v += hist[i];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) wsum[w] = v;
+    __syncthreads();
+    if (t == 0) seg[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// Exclusive prefix sum of segment b in place, starting from seg[b] (the
+// segment's offset). Thread t holds counts 4t .. 4t + 3 of the segment; total
+// is a multiple of 256, so a thread's four counts are all in range or none.
+__global__ __launch_bounds__(256) void k_scan_seg_apply(uint32_t *__restrict__ hist, int64_t total,
+                                                        const uint32_t *__restrict__ seg) {
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t i = (int64_t)blockIdx.x * kScanSeg + 4 * t;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (i < total) v = *reinterpret_cast<const uint4 *>(hist + i);
+    const uint32_t own = v.x + v.y + v.z + v.w;
+    uint32_t x = own;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t before = seg[blockIdx.x] + x - own;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    if (i < total) {
+        uint4 o;
+        o.x = before;
+        o.y = o.x + v.x;
+        o.z = o.y + v.y;
+        o.w = o.z + v.z;
+        *reinterpret_cast<uint4 *>(hist + i) = o;
+    }
+}
+
+// Exclusive prefix sum over hist[total] in one block (the top level of the
+// two-level sum above).
 __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ hist, int64_t total) {
     // exclusive prefix sum in place, 1024 consecutive counts at a time:
     // coalesced loads, a shuffle scan per wave, the 16 wave totals scanned in
@@ -399,9 +462,46 @@ __device__ __forceinline__ void range_union(int64_t a, int64_t e, const float *_
     acc.wave_union();
 }
 
-// Child boxes of every internal node (one wave per node): the left child
-// covers leaves [lo, gamma], the right [gamma + 1, hi], gamma being the left
-// child's last leaf; node 0's union is the root box in the header.
+// Nodes over at most kLaneRange leaves (most of them: every level below the
+// top log2(n / kLaneRange) or so) are refit by one lane each; the others by
+// one wave each. The two kernels write disjoint nodes.
+constexpr int64_t kLaneRange = 32;
+
+// Root box in the header from node 0's two child boxes.
+__device__ __forceinline__ void store_root(float *__restrict__ header, const float *l_lo, const float *l_hi,
+                                           const float *r_lo, const float *r_hi) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        header[6 + a] = fminf(l_lo[a], r_lo[a]);
+        header[9 + a] = fmaxf(l_hi[a], r_hi[a]);
+    }
+}
+
+// Child boxes of the internal nodes over at most kLaneRange leaves, one lane
+// per node: the left child covers leaves [lo, gamma], the right
+// [gamma + 1, hi], gamma being the left child's last leaf.
+__global__ __launch_bounds__(256) void k_refit_lanes(int64_t n, const float *__restrict__ leaf_box,
+                                                     float *__restrict__ nodes, float *__restrict__ header) {
+    if (!tree_matches(header, n)) return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n - 1) return;
+    float *rec = nodes + 16 * i;
+    const int64_t lo = __float_as_int(rec[14]), hi = __float_as_int(rec[15]);
+    if (hi - lo + 1 > kLaneRange) return;
+    const int32_t left = __float_as_int(rec[12]);
+    const int64_t gamma = left < 0 ? (int64_t)~left : (int64_t)left;
+    BoxAcc l, r;
+    l.reset();
+    r.reset();
+    for (int64_t m = lo; m <= gamma; ++m) l.add(leaf_box + 6 * m);
+    for (int64_t m = gamma + 1; m <= hi; ++m) r.add(leaf_box + 6 * m);
+    l.store(rec);
+    r.store(rec + 6);
+    if (i == 0) store_root(header, l.lo, l.hi, r.lo, r.hi);
+}
+
+// Child boxes of the internal nodes over more than kLaneRange leaves, one
+// wave per node; node 0's union is the root box in the header.
 __global__ __launch_bounds__(256) void k_refit_ranges(int64_t n, const float *__restrict__ leaf_box,
                                                       const float *__restrict__ block_box, float *__restrict__ nodes,
                                                       float *__restrict__ header) {
@@ -409,8 +509,9 @@ __global__ __launch_bounds__(256) void k_refit_ranges(int64_t n, const float *__
     const int lane = threadIdx.x & 63;
     for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n - 1; i += (int64_t)gridDim.x * 4) {
         float *rec = nodes + 16 * i;
-        const int32_t left = __float_as_int(rec[12]);
         const int64_t lo = __float_as_int(rec[14]), hi = __float_as_int(rec[15]);
+        if (hi - lo + 1 <= kLaneRange) continue;
+        const int32_t left = __float_as_int(rec[12]);
         // the split gamma is the left child's index, whether leaf (~gamma) or node
         const int64_t gamma = left < 0 ? (int64_t)~left : (int64_t)left;
         BoxAcc l, r;
@@ -419,13 +520,7 @@ __global__ __launch_bounds__(256) void k_refit_ranges(int64_t n, const float *__
         if (lane == 0) {
             l.store(rec);
             r.store(rec + 6);
-            if (i == 0) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    header[6 + a] = fminf(l.lo[a], r.lo[a]);
-                    header[9 + a] = fmaxf(l.hi[a], r.hi[a]);
-                }
-            }
+            if (i == 0) store_root(header, l.lo, l.hi, r.lo, r.hi);
         }
     }
 }
@@ -443,6 +538,8 @@ inline void launch_refit(int64_t n, const float *leaf_box, float *block_box, flo
         const int64_t nb = (n + kBoxBlock - 1) / kBoxBlock;
         hipLaunchKernelGGL(k_block_boxes, dim3((unsigned)std::min<int64_t>((nb + 3) / 4, 65536)), dim3(256), 0, s,
                            n, leaf_box, block_box, header);
+        hipLaunchKernelGGL(k_refit_lanes, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, n, leaf_box, nodes,
+                           header);
         hipLaunchKernelGGL(k_refit_ranges, dim3((unsigned)std::min<int64_t>((n - 1 + 3) / 4, 65536)), dim3(256), 0,
                            s, n, leaf_box, block_box, nodes, header);
     } else {
@@ -615,6 +712,7 @@ extern "C" rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
     uint64_t *keys_tmp = at<uint64_t>(ws, W.keys_tmp);
     uint32_t *vals_tmp = at<uint32_t>(ws, W.vals_tmp);
     uint32_t *hist = at<uint32_t>(ws, W.hist);
+    uint32_t *seg = at<uint32_t>(ws, W.seg);
     float *bpart = at<float>(ws, W.bounds);
     float *block_box = at<float>(ws, W.block_box);
 
@@ -632,7 +730,11 @@ extern "C" rv_status rv_build_bvh(const rv_gaussians *g, void *bvh, size_t bvh_b
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)W.nblocks), dim3(kSortWave), 0, s, ka, n, shift, hist,
                            W.nblocks);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * W.nblocks);
+        hipLaunchKernelGGL(k_scan_seg_sum, dim3((unsigned)W.nseg), dim3(256), 0, s, hist, (int64_t)256 * W.nblocks,
+                           seg);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, seg, W.nseg);
+        hipLaunchKernelGGL(k_scan_seg_apply, dim3((unsigned)W.nseg), dim3(256), 0, s, hist, (int64_t)256 * W.nblocks,
+                           seg);
         hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)W.nblocks), dim3(kSortWave), 0, s, ka, va, n, shift,
                            hist, W.nblocks, kb, vb);
         std::swap(ka, kb);

@@ -80,9 +80,12 @@ constexpr int kBoundsBlocks = 1024;
 // Leaves per block box of the refit (unions of consecutive sorted leaves).
 constexpr int64_t kBoxBlock = 256;
 
+// Counts per segment of the radix sort's two-level prefix sum.
+constexpr int64_t kScanSeg = 1024;
+
 struct BuildWsLayout {
-    size_t keys_tmp, vals_tmp, hist, bounds, block_box, total;
-    int64_t nblocks;
+    size_t keys_tmp, vals_tmp, hist, seg, bounds, block_box, total;
+    int64_t nblocks, nseg;
 };
 
 inline BuildWsLayout build_ws_layout(int64_t n) {
@@ -93,6 +96,8 @@ inline BuildWsLayout build_ws_layout(int64_t n) {
     W.keys_tmp = off; off = align_up(off + nn * 8);
     W.vals_tmp = off; off = align_up(off + nn * 4);
     W.hist = off; off = align_up(off + 256 * (size_t)W.nblocks * 4);
+    W.nseg = (256 * W.nblocks + kScanSeg - 1) / kScanSeg;
+    W.seg = off; off = align_up(off + (size_t)W.nseg * 4);
     W.bounds = off; off = align_up(off + kBoundsBlocks * 6 * sizeof(float));
     W.block_box = off; off = align_up(off + (size_t)((nn + kBoxBlock - 1) / kBoxBlock) * 6 * sizeof(float));
     W.total = off;
