@@ -396,6 +396,8 @@ size_t rv_surrogate_infer_workspace_bytes(int64_t q_count);
  * n_params floats, the flat order above) or, when it is NULL, a seeded
  * He-uniform draw from a counter-based hash of (seed, index) with zero biases;
  * Adam state zero; BF16 copies packed.
+ * Errors: RV_ERR_INVALID_ARG (null params or box, params not 256-byte
+ * aligned), RV_ERR_HIP (a launch failed).
  */
 rv_status rv_surrogate_init(void *params, uint64_t seed, const float *box_lo_host, const float *box_hi_host,
                             const float *init_weights, void *stream);
@@ -404,6 +406,9 @@ rv_status rv_surrogate_init(void *params, uint64_t seed, const float *box_lo_hos
  * Mean loss (loss_out, device float[1]) and its gradient (grad_out, device
  * float[n_params], overwritten) on samples 0..n-1 of (x [n][3], d [n][3],
  * T [n]); n <= the workspace's batch. Deterministic.
+ * Errors: RV_ERR_INVALID_ARG (a null pointer, n outside [1, 2^30], ws not
+ * 256-byte aligned), RV_ERR_WORKSPACE (ws_bytes below the training scratch of
+ * a batch of n), RV_ERR_HIP.
  */
 rv_status rv_surrogate_loss_grad(const void *params, const float *x, const float *d, const float *T, int64_t n,
                                  float *grad_out, float *loss_out, void *ws, size_t ws_bytes, void *stream);
@@ -412,11 +417,20 @@ rv_status rv_surrogate_loss_grad(const void *params, const float *x, const float
  * o->steps Adam steps on batches drawn from n_samples tracer samples (x [n][3],
  * d [n][3], T [n]). loss_log (device, FP32 [steps]; NULL to skip) receives
  * each step's mean loss.
+ * Errors: RV_ERR_INVALID_ARG (a null pointer, n_samples < 1, steps < 0, batch
+ * not a positive multiple of 128, lr < 0, beta1 or beta2 outside [0, 1),
+ * eps <= 0, ws not 256-byte aligned), RV_ERR_WORKSPACE (ws_bytes below
+ * rv_surrogate_train_workspace_bytes(batch)), RV_ERR_HIP.
  */
 rv_status rv_surrogate_train(void *params, const float *x, const float *d, const float *T, int64_t n_samples,
                              const rv_train_opts *o, float *loss_log, void *ws, size_t ws_bytes, void *stream);
 
-/* Free-form inference: vis[s], unc[s] (unc may be NULL) for n queries (x[s], d[s]). */
+/*
+ * Free-form inference: vis[s], unc[s] (unc may be NULL) for n queries
+ * (x[s], d[s]; device [n][3]). n = 0 is a no-op.
+ * Errors: RV_ERR_INVALID_ARG (null params or vis, null x or d with n > 0,
+ * n < 0), RV_ERR_HIP.
+ */
 rv_status rv_surrogate_infer_xd(const void *params, const float *x, const float *d, int64_t n, float *vis,
                                 float *unc, void *stream);
 
@@ -431,7 +445,13 @@ rv_status rv_surrogate_infer_xd(const void *params, const float *x, const float 
  * and traced by a persistent kernel; ws: 256-byte aligned,
  * rv_surrogate_infer_workspace_bytes(q_count) bytes, not shared by
  * overlapping calls. Deterministic (each query's value does not depend on
- * the list order).
+ * the list order). q_count = 0 is a no-op.
+ * Errors: RV_ERR_INVALID_ARG (a null pointer among params, g, dirs, p, vis;
+ * null means or log-scales, n outside [1, RV_MAX_GAUSSIANS], K < 1, dir_mode 1
+ * without normals, trace parameters out of range, the query range outside
+ * [0, n K), ws missing or unaligned), RV_ERR_WORKSPACE (ws_bytes below
+ * rv_surrogate_infer_workspace_bytes(q_count)), RV_ERR_HIP. A bvh built for
+ * another Gaussian set is not walked: its fallback queries give NaN.
  */
 rv_status rv_surrogate_infer(const void *params, const void *bvh, const rv_gaussians *g, const float *dirs,
                              int32_t K, const rv_trace_params *p, int64_t q_begin, int64_t q_count, float tau,
@@ -441,6 +461,10 @@ rv_status rv_surrogate_infer(const void *params, const void *bvh, const rv_gauss
 /*
  * Origin and unit direction of each listed ray (device, out_o/out_d [n][3]),
  * formed exactly as the tracer forms them: the training inputs of the surrogate.
+ * ray_ids (device int64 [n]) hold q = i*K + k. n = 0 is a no-op.
+ * Errors: RV_ERR_INVALID_ARG (null g, dirs, p or means; n outside
+ * [1, RV_MAX_GAUSSIANS] Gaussians, K < 1 or n < 0 rays; dir_mode 1 without
+ * normals; null ids or outputs with n > 0), RV_ERR_HIP.
  */
 rv_status rv_ray_setup(const rv_gaussians *g, const float *dirs, int32_t K, const rv_trace_params *p,
                        const int64_t *ray_ids, int64_t n, float *out_o, float *out_d, void *stream);

@@ -1319,7 +1319,8 @@ extern "C" rv_status rv_surrogate_infer(const void *params, const void *bvh, con
                                         size_t ws_bytes, void *stream) {
     clear_error();
     RV_REQUIRE(params && g && dirs && p && vis, RV_ERR_INVALID_ARG, "rv_surrogate_infer: null argument");
-    RV_REQUIRE(g->mean && g->log_scale && g->n >= 1 && K >= 1, RV_ERR_INVALID_ARG, "rv_surrogate_infer: bad scene");
+    RV_REQUIRE(g->mean && g->log_scale && g->n >= 1 && g->n <= RV_MAX_GAUSSIANS && K >= 1, RV_ERR_INVALID_ARG,
+               "rv_surrogate_infer: bad scene (null arrays, n out of range or K < 1)");
     RV_REQUIRE(p->dir_mode == 0 || (p->dir_mode == 1 && g->normal), RV_ERR_INVALID_ARG,
                "rv_surrogate_infer: bad dir_mode or missing normals");
     RV_REQUIRE(p->sigma_cut > 0.0f && p->sigma_cut <= kBuildSigma && p->alpha_min > 0.0f && p->alpha_max < 1.0f &&
@@ -1382,7 +1383,8 @@ extern "C" rv_status rv_ray_setup(const rv_gaussians *g, const float *dirs, int3
                                   const int64_t *ray_ids, int64_t n, float *out_o, float *out_d, void *stream) {
     clear_error();
     RV_REQUIRE(g && dirs && p && g->mean, RV_ERR_INVALID_ARG, "rv_ray_setup: null argument");
-    RV_REQUIRE(g->n >= 1 && K >= 1 && n >= 0, RV_ERR_INVALID_ARG, "rv_ray_setup: bad sizes");
+    RV_REQUIRE(g->n >= 1 && g->n <= RV_MAX_GAUSSIANS && K >= 1 && n >= 0, RV_ERR_INVALID_ARG,
+               "rv_ray_setup: bad sizes");
     RV_REQUIRE(p->dir_mode == 0 || (p->dir_mode == 1 && g->normal), RV_ERR_INVALID_ARG,
                "rv_ray_setup: bad dir_mode or missing normals");
     if (n == 0) return RV_OK;

@@ -246,3 +246,70 @@ def test_wrappers_reject_a_tree_of_another_gaussian_set():
     net.device = torch.device("cpu")
     with pytest.raises(ValueError, match="built over 11 Gaussians"):
         net.infer_grid(g, dirs, bvh=bvh)
+
+
+def _opts(**kw):
+    o = dict(steps=1, batch=256, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, lr_min=1e-5, seed=0, step0=0,
+             total_steps=1)
+    o.update(kw)
+    return _lib.RvTrainOpts(**o)
+
+
+def test_surrogate_rejects_bad_arguments(lib):
+    P = 1 << 40
+    INV, WS = _lib.RV_ERR_INVALID_ARG, _lib.RV_ERR_WORKSPACE
+    assert lib.rv_surrogate_init(None, 0, P, P, None, None) == INV
+    assert lib.rv_surrogate_init(P + 16, 0, P, P, None, None) == INV   # blob not 256-byte aligned
+    ws = lib.rv_surrogate_train_workspace_bytes(256)
+    assert ws > 0 and ws % 256 == 0
+    tr = lib.rv_surrogate_train
+    assert tr(None, P, P, P, 100, C.byref(_opts()), P, P, ws, None) == INV
+    assert tr(P, P, P, P, 0, C.byref(_opts()), P, P, ws, None) == INV          # no samples
+    for bad in (dict(steps=-1), dict(batch=0), dict(batch=100), dict(lr=-1.0), dict(beta1=1.0), dict(beta2=1.0),
+                dict(beta1=-0.1), dict(eps=0.0)):
+        assert tr(P, P, P, P, 100, C.byref(_opts(**bad)), P, P, ws, None) == INV, bad
+    assert tr(P, P, P, P, 100, C.byref(_opts()), P, P + 64, ws, None) == INV    # workspace not aligned
+    assert tr(P, P, P, P, 100, C.byref(_opts()), P, P, ws - 256, None) == WS
+    lg = lib.rv_surrogate_loss_grad
+    assert lg(P, P, P, P, 0, P, P, P, ws, None) == INV
+    assert lg(P, P, P, P, (1 << 30) + 1, P, P, P, ws, None) == INV
+    assert lg(P, P, P, P, 256, P, P, P, ws - 256, None) == WS
+    xd = lib.rv_surrogate_infer_xd
+    assert xd(P, P, P, -1, P, None, None) == INV
+    assert xd(P, None, P, 4, P, None, None) == INV
+    assert xd(P, None, None, 0, P, None, None) == 0                            # n = 0: no-op
+    g, p = _g(), _params()
+    inf = lib.rv_surrogate_infer
+    need = lib.rv_surrogate_infer_workspace_bytes(80)
+    assert need % 256 == 0 and need >= 256 + 80 * 9
+    assert inf(P, None, None, P, 8, C.byref(p), 0, 80, 0.1, P, None, None, P, need, None) == INV
+    assert inf(P, None, C.byref(g), P, 0, C.byref(p), 0, 80, 0.1, P, None, None, P, need, None) == INV   # K = 0
+    assert inf(P, None, C.byref(_g(1 << 31)), P, 8, C.byref(p), 0, 80, 0.1, P, None, None, P, need,
+               None) == INV                                                   # n beyond RV_MAX_GAUSSIANS
+    assert inf(P, None, C.byref(_g(normal=False)), P, 8, C.byref(p), 0, 80, 0.1, P, None, None, P, need,
+               None) == INV                                                   # hemisphere without normals
+    assert inf(P, None, C.byref(g), P, 8, C.byref(_params(sigma_cut=4.0)), 0, 80, 0.1, P, None, None, P, need,
+               None) == INV
+    assert inf(P, None, C.byref(g), P, 8, C.byref(p), 1, 80, 0.1, P, None, None, P, need, None) == INV   # past n K
+    assert inf(P, None, C.byref(g), P, 8, C.byref(p), -1, 10, 0.1, P, None, None, P, need, None) == INV
+    assert inf(P, None, C.byref(g), P, 8, C.byref(p), 0, 80, 0.1, P, None, None, None, need, None) == INV
+    assert inf(P, None, C.byref(g), P, 8, C.byref(p), 0, 80, 0.1, P, None, None, P + 64, need, None) == INV
+    assert inf(P, None, C.byref(g), P, 8, C.byref(p), 0, 80, 0.1, P, None, None, P, need - 256, None) == WS
+    assert inf(P, None, C.byref(g), P, 8, C.byref(p), 80, 0, 0.1, P, None, None, None, 0, None) == 0  # empty range
+    assert lib.rv_last_error() is not None
+
+
+def test_ray_setup_rejects_bad_arguments(lib):
+    P = 1 << 40
+    INV = _lib.RV_ERR_INVALID_ARG
+    g, p = _g(), _params()
+    f = lib.rv_ray_setup
+    assert f(None, P, 8, C.byref(p), P, 4, P, P, None) == INV
+    assert f(C.byref(g), P, 0, C.byref(p), P, 4, P, P, None) == INV             # K = 0
+    assert f(C.byref(g), P, 8, C.byref(p), P, -1, P, P, None) == INV            # n < 0
+    assert f(C.byref(_g(0)), P, 8, C.byref(p), P, 4, P, P, None) == INV
+    assert f(C.byref(_g(1 << 31)), P, 8, C.byref(p), P, 4, P, P, None) == INV
+    assert f(C.byref(_g(normal=False)), P, 8, C.byref(p), P, 4, P, P, None) == INV
+    assert f(C.byref(g), P, 8, C.byref(p), None, 4, P, P, None) == INV          # no ids
+    assert f(C.byref(g), P, 8, C.byref(p), P, 4, P, None, None) == INV          # no output
+    assert f(C.byref(g), P, 8, C.byref(p), None, 0, None, None, None) == 0      # n = 0: no-op
