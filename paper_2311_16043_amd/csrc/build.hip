@@ -127,16 +127,28 @@ __global__ __launch_bounds__(kSortWave) void k_sort_hist(const uint64_t *__restr
     for (int i = lane; i < 256; i += kSortWave) h[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int j = 0; j < kSortItems; ++j) {
-        int64_t idx = base + (int64_t)j * kSortWave + lane;
-        bool ok = idx < n;
-        uint32_t d = ok ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
-        uint64_t valid = __ballot(ok);
-        if (valid == 0) break;
-        uint64_t peers = match_digit8(d, valid);
-        // the lowest lane of each group adds the group's size
-        if (ok && (peers & ((1ull << lane) - 1ull)) == 0) h[d] += (uint32_t)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
+    for (int j0 = 0; j0 < kSortItems && base + (int64_t)j0 * kSortWave < n; j0 += kSortAhead) {
+        // the next kSortAhead keys of this lane are in flight together:
+        // unconditional loads (past the end: the last key, discarded) so that
+        // none waits behind a branch
+        uint64_t kv[kSortAhead];
+        bool ok[kSortAhead];
+#pragma unroll
+        for (int u = 0; u < kSortAhead; ++u) {
+            const int64_t idx = base + (int64_t)(j0 + u) * kSortWave + lane;
+            ok[u] = idx < n;
+            kv[u] = keys[ok[u] ? idx : n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kSortAhead; ++u) {
+            const uint32_t d = ok[u] ? (uint32_t)(kv[u] >> shift) & 255u : 0u;
+            const uint64_t valid = __ballot(ok[u]);
+            if (valid == 0) break;
+            const uint64_t peers = match_digit8(d, valid);
+            // the lowest lane of each group adds the group's size
+            if (ok[u] && (peers & ((1ull << lane) - 1ull)) == 0) h[d] += (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+        }
     }
     __syncthreads();
     for (int i = lane; i < 256; i += kSortWave) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
@@ -246,24 +258,37 @@ __global__ __launch_bounds__(kSortWave) void k_sort_scatter(const uint64_t *__re
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (int j = 0; j < kSortItems; ++j) {
-        int64_t idx = base + (int64_t)j * kSortWave + lane;
-        bool ok = idx < n;
-        uint64_t key = ok ? kin[idx] : 0ull;
-        uint32_t val = ok ? vin[idx] : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & 255u;
-        uint64_t valid = __ballot(ok);
-        if (valid == 0) break;
-        uint64_t peers = match_digit8(d, valid);
-        uint32_t rank = (uint32_t)__popcll(peers & lt);
-        uint32_t pos = ok ? offs[d] + rank : 0u;
-        __builtin_amdgcn_wave_barrier();
-        // every lane has read its group's offset; the group leader advances it
-        if (ok && rank == 0) offs[d] = pos + (uint32_t)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-        if (ok) {
-            kout[pos] = key;
-            vout[pos] = val;
+    for (int j0 = 0; j0 < kSortItems && base + (int64_t)j0 * kSortWave < n; j0 += kSortAhead) {
+        // the next kSortAhead items of this lane are loaded together, then
+        // ranked strictly in order (the sort stays stable)
+        uint64_t key[kSortAhead];
+        uint32_t val[kSortAhead];
+        bool ok[kSortAhead];
+#pragma unroll
+        for (int u = 0; u < kSortAhead; ++u) {
+            // unconditional loads (past the end: the last item, discarded)
+            const int64_t idx = base + (int64_t)(j0 + u) * kSortWave + lane;
+            ok[u] = idx < n;
+            const int64_t at_idx = ok[u] ? idx : n - 1;
+            key[u] = kin[at_idx];
+            val[u] = vin[at_idx];
+        }
+#pragma unroll
+        for (int u = 0; u < kSortAhead; ++u) {
+            const uint32_t d = (uint32_t)(key[u] >> shift) & 255u;
+            const uint64_t valid = __ballot(ok[u]);
+            if (valid == 0) break;
+            const uint64_t peers = match_digit8(d, valid);
+            const uint32_t rank = (uint32_t)__popcll(peers & lt);
+            const uint32_t pos = ok[u] ? offs[d] + rank : 0u;
+            __builtin_amdgcn_wave_barrier();
+            // every lane has read its group's offset; the group leader advances it
+            if (ok[u] && rank == 0) offs[d] = pos + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+            if (ok[u]) {
+                kout[pos] = key[u];
+                vout[pos] = val[u];
+            }
         }
     }
 }

@@ -75,6 +75,8 @@ inline BvhLayout bvh_layout(int64_t n) {
 constexpr int kSortWave = 64;
 constexpr int kSortItems = 32;
 constexpr int kSortTile = kSortWave * kSortItems;
+constexpr int kSortAhead = 4;  // items per lane loaded ahead of their ranking
+static_assert(kSortItems % kSortAhead == 0, "sort tile must hold whole load groups");
 constexpr int kBoundsBlocks = 1024;
 
 // Leaves per block box of the refit (unions of consecutive sorted leaves).
