@@ -63,12 +63,13 @@ constexpr int kStreamRing = 16;
 // against 53.7 with two and 54.5 with four at object scale.
 constexpr int kStreamPoolS = 1;
 constexpr int kLeafMin = 32;
-// Idle lanes that trigger a refill of a wave, unless no lane holds a ray.
-// Refilling at every finished ray ran the ray setup for one or two lanes
-// nearly every iteration; waiting for 12 idle lanes costs a few lanes of
-// traversal and saves most of those setups (object scale: 43.6 -> 40.4 ms,
+// Idle lanes that trigger a refill of a wave in the adjoint, unless no lane
+// holds a ray (the forward kernels take Cuts::refill, set from the tree's
+// size). Refilling at every finished ray ran the ray setup for one or two
+// lanes nearly every iteration; waiting for 12 idle lanes costs a few lanes
+// of traversal and saves most of those setups (object scale: 43.6 -> 40.4 ms,
 // adjoint 59.7 -> 58.2 ms).
-constexpr int kRefillMin = 12;
+constexpr int kRefillMin = kRefillShallow;
 
 struct PoolMap {
     int64_t n;
@@ -205,7 +206,7 @@ struct RangeQueue {
 };
 
 // Trace the rays of the pools the queue hands out with the lanes of one
-// wave. Once kRefillMin lanes are without a ray (or no lane has one), those
+// wave. Once c.refill lanes are without a ray (or no lane has one), those
 // lanes take the next rays of the current pool; when the pool is spent the
 // wave takes the next pool at once, so lanes stay supplied across pool
 // boundaries. A finished
@@ -238,10 +239,10 @@ __device__ __forceinline__ void stream_rays(const float4 *__restrict__ nodes4, c
 
     while (true) {
         // refill idle lanes, moving on to further pools while lanes are idle;
-        // only once kRefillMin lanes are idle (or none holds a ray), so that
+        // only once c.refill lanes are idle (or none holds a ray), so that
         // the ray setup runs for several lanes at a time
         uint64_t need = __ballot(!has);
-        if (__popcll(need) < kRefillMin && __ballot(has) != 0) need = 0;
+        if (__popcll(need) < c.refill && __ballot(has) != 0) need = 0;
         while (need != 0 && more) {
             if (next >= pool_n) {
                 int64_t p;
@@ -961,12 +962,14 @@ void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs
     if (n_list <= 0) return;
     const BvhLayout L = bvh_layout(g->n);
     const int64_t pools = (n_list + kPoolS * 64 - 1) / (kPoolS * 64);
+    Cuts cc = c;
+    cc.refill = refill_lanes(g->n);
     if (queues) {
         hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t *>(queues),
                            (int64_t)(2 * kXcds), 0u);
         hipLaunchKernelGGL(k_trace_list<true>, dim3((unsigned)stream_blocks(pools)), dim3(kTraceBlock), 0, stream,
                            at<float>(bvh, L.header), at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), g->mean,
-                           c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, c, ids, n_list, count,
+                           c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, cc, ids, n_list, count,
                            id_offset, out_by_value ? 1 : 0, (int64_t)0, queues, out);
         return;
     }
@@ -975,7 +978,7 @@ void launch_trace_list(const void *bvh, const rv_gaussians *g, const float *dirs
     hipLaunchKernelGGL(k_trace_list<false>, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
                        dim3(kTraceBlock), 0, stream, at<float>(bvh, L.header), at<float4>(bvh, L.nodes4),
                        at<float4>(bvh, L.leaf_rec), g->mean,
-                       c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, c, ids, n_list, count, id_offset,
+                       c.dir_mode ? g->normal : nullptr, g->log_scale, g->n, dirs, K, cc, ids, n_list, count, id_offset,
                        out_by_value ? 1 : 0, run, (unsigned long long *)nullptr, out);
 }
 
@@ -1003,9 +1006,11 @@ void launch_trace_stream(const void *bvh, const rv_gaussians *g, const float *di
     auto *queues = static_cast<unsigned long long *>(ws);
     hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(queues),
                        (int64_t)(2 * kXcds), 0u);
+    Cuts cc = c;
+    cc.refill = refill_lanes(g->n);
     hipLaunchKernelGGL(k_trace_stream<kCount>, dim3((unsigned)stream_blocks(n_pools)), dim3(kTraceBlock), 0, s,
                        at<float>(bvh, L.header), at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs, g->n,
-                       K, c, m_lo, m_hi, by_leaf ? 1 : 0, queues, vis_ray, totals);
+                       K, cc, m_lo, m_hi, by_leaf ? 1 : 0, queues, vis_ray, totals);
 }
 
 // Enqueue the all-ray trace with its scratch at ws (256-byte aligned: the
