@@ -641,8 +641,13 @@ __global__ __launch_bounds__(256) void k_sh_rows(const float *__restrict__ rows,
 // trace 64 adjacent origins x 16 directions, whose hits concentrate on the
 // same nearby Gaussians, so their seven sums are added in LDS and flushed
 // with one set of global atomics per Gaussian at the end of the block.
+// A Gaussian tries kHashProbes consecutive slots before its hit goes to the
+// global atomics: once the table has filled, every further probe is a
+// compare-and-swap that cannot succeed (2 / 4 / 8 / 16 probes: 59.5 / 57.7 /
+// 57.8 / 60.9 ms with the forward's T, 88.3 / 90.2 / 94.6 / 104.0 ms
+// re-tracing).
 constexpr int kHashSlots = 1024;
-constexpr int kHashProbes = 8;
+constexpr int kHashProbes = 4;
 
 struct GradTable {
     int32_t key[kHashSlots];         // Gaussian index, -1 when free
