@@ -326,6 +326,11 @@ rv_status rv_gather_probe(const void *table, int64_t n_records, int32_t rounds, 
  * clamp are not differentiated. Gradients are ACCUMULATED (+=) into the
  * caller's buffers with FP32 atomics: zero them first; the summation order,
  * hence the last bits, may vary between runs.
+ * The call takes 256 MB of device scratch, stream-ordered on `stream`
+ * (hipMallocAsync, released by hipFreeAsync after its launches), for the hits
+ * that overflow each block's on-chip accumulation table; if that allocation
+ * fails, those hits are added with atomics at once (same result up to the
+ * summation order). Calls on different streams take separate scratch.
  */
 rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaussians *g, const float *dirs, int32_t K,
                                        const rv_trace_params *p, const float *grad_vis_ray,

@@ -660,13 +660,23 @@ __global__ __launch_bounds__(256) void k_sh_rows(const float *__restrict__ rows,
 // Per-block accumulation table of the scatter: the four waves of a block
 // trace 64 adjacent origins x 16 directions, whose hits concentrate on the
 // same nearby Gaussians, so their seven sums are added in LDS and flushed
-// with one set of global atomics per Gaussian at the end of the block.
+// with one set of global atomics per Gaussian at the end of the block. Hits
+// whose Gaussian finds no slot are kept as records in a buffer of the block's
+// own; once the table is flushed, a second pass sums the records per Gaussian
+// in the emptied table and flushes it again.
 // A Gaussian tries kHashProbes consecutive slots before its hit goes to the
 // global atomics: once the table has filled, every further probe is a
 // compare-and-swap that cannot succeed (2 / 4 / 8 / 16 probes: 59.5 / 57.7 /
 // 57.8 / 60.9 ms with the forward's T, 88.3 / 90.2 / 94.6 / 104.0 ms
 // re-tracing).
 constexpr int kHashSlots = 1024;
+// Record buffers for the hits that overflow a block's table: more buffers
+// than blocks can be resident (3 per CU), 8,192 records (256 KB) each, 256 MB
+// in all. Against seven device atomics per overflowing hit, the second pass
+// takes the adjoint with the forward's T from 57.3 to 50.6 ms at object scale
+// (200k x 128; 4,096 records: 51.7 ms, 16,384: 51.8 ms; 16 or 32 probes in the
+// second pass: no change).
+constexpr int kOvfSlots = 1024, kOvfCap = 8192;
 constexpr int kHashProbes = 4;
 
 struct GradTable {
@@ -686,12 +696,27 @@ struct GradTable {
     }
 };
 
+// Seven sums of Gaussian j added with device-scope atomics.
+__device__ __forceinline__ void add_grad_global(float *go, float *gm, float *gl, int64_t j, const float (&v)[7]) {
+    unsafeAtomicAdd(go + j, v[0]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        unsafeAtomicAdd(gm + 3 * j + c, v[1 + c]);
+        unsafeAtomicAdd(gl + 3 * j + c, v[4 + c]);
+    }
+}
+
 struct GradScatter {
     bool active;        // false on the pass that only recovers T_final
     float g_over;       // -(dL/dT) * T_final for the current ray
     float *go, *gm, *gl;
     GradTable *table;
     f3 origin;          // accumulated d/d(origin) of the current ray
+    // the block's overflow records (two float4 each: source index and the
+    // seven sums), or null; *ovf_n counts the records claimed (LDS)
+    float4 *ovf;
+    int *ovf_n;
+    int ovf_cap;
 
     __device__ __forceinline__ void operator()(const LeafHit &h, float) {
         if (!active || h.clamped) return;
@@ -705,12 +730,14 @@ struct GradScatter {
 #pragma unroll
             for (int c = 0; c < 7; ++c) atomicAdd(&table->val[c][slot], v[c]);
         } else {
-            const int64_t j = h.src;
-            unsafeAtomicAdd(go + j, v[0]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                unsafeAtomicAdd(gm + 3 * j + c, v[1 + c]);
-                unsafeAtomicAdd(gl + 3 * j + c, v[4 + c]);
+            // no slot: keep the hit for the block's second pass when its
+            // record buffer has room, else add it to the gradients at once
+            const int r = ovf ? atomicAdd(ovf_n, 1) : ovf_cap;
+            if (r < ovf_cap) {
+                ovf[2 * r] = make_float4(__int_as_float(h.src), v[0], v[1], v[2]);
+                ovf[2 * r + 1] = make_float4(v[3], v[4], v[5], v[6]);
+            } else {
+                add_grad_global(go, gm, gl, h.src, v);
             }
         }
         origin = origin - a * wte;
@@ -723,12 +750,16 @@ struct GradScatter {
 // recover T_final (skipped when the forward's T are given), then again with
 // the same visits in the same order, scattering dL/dalpha_j = -g T_final /
 // (1 - alpha_j) into each included, unclamped Gaussian's parameters (through
-// the block's LDS table). The source's own term (through the ray origin) is
-// summed per Gaussian in LDS and added once per wave.
+// the block's LDS table and its overflow records). The source's own term
+// (through the ray origin) is summed per Gaussian in LDS and added once per
+// wave. ovf_buf holds ovf_slots record buffers of ovf_cap records, each owned
+// by the block that claimed its flag in ovf_flags (zero when free); null:
+// every overflowing hit is added at once.
 __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     const float *__restrict__ header, const float4 *__restrict__ nodes4, const float4 *__restrict__ rec, const float4 *__restrict__ origins,
     const float *__restrict__ dirs, PoolMap pm, Cuts c, const float *__restrict__ grad_ray,
-    const float *__restrict__ grad_mean_in, const float *__restrict__ vis_fwd, float *go, float *gm, float *gl) {
+    const float *__restrict__ grad_mean_in, const float *__restrict__ vis_fwd, float *go, float *gm, float *gl,
+    float4 *ovf_buf, uint32_t *ovf_flags, int ovf_slots, int ovf_cap) {
     __shared__ int32_t stk[kPoolRing * kTraceBlock];
     __shared__ int32_t fifo[kFifo * kTraceBlock];
     __shared__ float ogr[kWavesPerBlock][64 * 3];   // origin terms per item
@@ -738,6 +769,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     __shared__ int item_n[kWavesPerBlock], item_nv[kWavesPerBlock], item_k0[kWavesPerBlock];
     __shared__ int64_t item_m0[kWavesPerBlock];
     __shared__ int blk_next;
+    __shared__ int ovf_slot, ovf_n;   // the block's record buffer (-1: none) and its records
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (!tree_matches(header, pm.n)) {
         // a tree built for another Gaussian set: every gradient is NaN
@@ -754,6 +786,20 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
         table.key[s] = -1;
 #pragma unroll
         for (int c = 0; c < 7; ++c) table.val[c][s] = 0.0f;
+    }
+    if (threadIdx.x == 0) {
+        // claim a free record buffer: at most one pass over the flags, so a
+        // block never waits on another (without one, overflow goes out at once)
+        int got = -1;
+        if (ovf_buf) {
+            const int start = (int)(blockIdx.x % (unsigned)ovf_slots);
+            for (int i = 0; i < ovf_slots && got < 0; ++i) {
+                const int sl = start + i < ovf_slots ? start + i : start + i - ovf_slots;
+                if (atomicCAS(ovf_flags + sl, 0u, 1u) == 0u) got = sl;
+            }
+        }
+        ovf_slot = got;
+        ovf_n = 0;
     }
     // item wv: every wave reaches the barriers; items past the end are empty
     int64_t w = pm.w_off + xcd_chunk_block<kAdjChunk>(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
@@ -810,6 +856,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
     gs.gl = gl;
     gs.table = &table;
     gs.origin = mk(0.f, 0.f, 0.f);
+    gs.ovf = ovf_slot >= 0 ? ovf_buf + 2 * (int64_t)ovf_slot * ovf_cap : nullptr;
+    gs.ovf_n = &ovf_n;
+    gs.ovf_cap = ovf_cap;
     bool drained = false;  // wave-uniform: the block's rays are all handed out
     auto restart = [&]() {
         T = 1.0f;
@@ -905,16 +954,46 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_backward(
         }
     }
     // the block's table: one set of global atomics per Gaussian
+    auto flush_table = [&]() {
+        for (int s = threadIdx.x; s < kHashSlots; s += kTraceBlock) {
+            const int64_t j = table.key[s];
+            if (j < 0) continue;
+            const float v[7] = {table.val[0][s], table.val[1][s], table.val[2][s], table.val[3][s],
+                                table.val[4][s], table.val[5][s], table.val[6][s]};
+            add_grad_global(go, gm, gl, j, v);
+        }
+    };
+    flush_table();
+    if (ovf_slot < 0) return;   // block-uniform
+    // second pass: the hits that found no slot, summed per Gaussian in the
+    // emptied table (most of them now fit), then flushed once more
+    __syncthreads();
     for (int s = threadIdx.x; s < kHashSlots; s += kTraceBlock) {
-        const int64_t j = table.key[s];
-        if (j < 0) continue;
-        unsafeAtomicAdd(go + j, table.val[0][s]);
+        table.key[s] = -1;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            unsafeAtomicAdd(gm + 3 * j + c, table.val[1 + c][s]);
-            unsafeAtomicAdd(gl + 3 * j + c, table.val[4 + c][s]);
+        for (int c = 0; c < 7; ++c) table.val[c][s] = 0.0f;
+    }
+    __syncthreads();
+    const float4 *rec_ovf = ovf_buf + 2 * (int64_t)ovf_slot * ovf_cap;
+    const int n_rec = min(ovf_n, ovf_cap);
+    for (int r = threadIdx.x; r < n_rec; r += kTraceBlock) {
+        const float4 a = rec_ovf[2 * r], b = rec_ovf[2 * r + 1];
+        const int32_t j = __float_as_int(a.x);
+        const float v[7] = {a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        const int slot = table.find(j);
+        if (slot >= 0) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) atomicAdd(&table.val[c][slot], v[c]);
+        } else {
+            add_grad_global(go, gm, gl, j, v);
         }
     }
+    __syncthreads();
+    flush_table();
+    // every record has been read: hand the buffer back
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) atomicExch(ovf_flags + ovf_slot, 0u);
 }
 
 __global__ __launch_bounds__(64) void k_fill_u32_trace(uint32_t *__restrict__ p, int64_t count, uint32_t v) {
@@ -1168,15 +1247,31 @@ extern "C" rv_status rv_trace_visibility_backward(const void *bvh, const rv_gaus
     const PoolMap pm = make_pool(g->n, K);
     const BvhLayout L = bvh_layout(g->n);
     const Cuts c = make_cuts(*p);
+    // record buffers of the blocks' second pass (stream-ordered, freed after
+    // the launches); without them every overflowing hit goes out at once
+    hipStream_t s = (hipStream_t)stream;
+    const size_t flag_bytes = align_up((size_t)kOvfSlots * sizeof(uint32_t));
+    const size_t ovf_bytes = flag_bytes + (size_t)kOvfSlots * kOvfCap * 2 * sizeof(float4);
+    void *ovf_mem = nullptr;
+    if (hipMallocAsync(&ovf_mem, ovf_bytes, s) != hipSuccess) {
+        ovf_mem = nullptr;
+        (void)hipGetLastError();
+    }
+    uint32_t *ovf_flags = static_cast<uint32_t *>(ovf_mem);
+    float4 *ovf_buf = ovf_mem ? reinterpret_cast<float4 *>(static_cast<char *>(ovf_mem) + flag_bytes) : nullptr;
+    if (ovf_mem) hipLaunchKernelGGL(k_fill_u32_trace, dim3(1), dim3(64), 0, s, ovf_flags, (int64_t)kOvfSlots, 0u);
     for (int64_t w0 = 0; w0 < pm.n_items; w0 += kLaunchWaves) {
         PoolMap part = pm;
         part.w_off = w0;
         const int64_t nb = (std::min(kLaunchWaves, pm.n_items - w0) + kWavesPerBlock - 1) / kWavesPerBlock;
-        hipLaunchKernelGGL(k_trace_backward, dim3((unsigned)nb), dim3(kTraceBlock), 0, (hipStream_t)stream,
+        hipLaunchKernelGGL(k_trace_backward, dim3((unsigned)nb), dim3(kTraceBlock), 0, s,
                            at<float>(bvh, L.header), at<float4>(bvh, L.nodes4), at<float4>(bvh, L.leaf_rec), at<float4>(bvh, L.origins), dirs,
-                           part, c, grad_vis_ray, grad_vis_mean, vis_ray_fwd, grad_opacity, grad_mean, grad_log_scale);
+                           part, c, grad_vis_ray, grad_vis_mean, vis_ray_fwd, grad_opacity, grad_mean, grad_log_scale,
+                           ovf_buf, ovf_flags, kOvfSlots, kOvfCap);
     }
-    return check_launch("rv_trace_visibility_backward");
+    const rv_status st_launch = check_launch("rv_trace_visibility_backward");
+    if (ovf_mem) (void)hipFreeAsync(ovf_mem, s);
+    return st_launch;
 }
 
 extern "C" size_t rv_trace_sh_workspace_bytes(int64_t n, int32_t K) {
