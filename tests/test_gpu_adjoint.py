@@ -1,7 +1,8 @@
 """Adjoint of the tracer: d/d(opacity, mean, log_scale) of sum_r g_r T_r.
 
 1. Small scene: the GPU adjoint against the oracle's analytic FP64 gradient
-   (itself pinned to finite differences in test_oracle_pins.py), every ray.
+   (itself pinned to finite differences in test_oracle_pins.py), every ray;
+   also a denser variant whose blocks overflow their gradient tables.
 2. Differentiation workload at full size (200,000 object-scale Gaussians x 128
    hemisphere directions): 64 seeded parameters against FP64 central finite
    differences of the oracle (h = 1e-4, plus a Richardson step), relative
@@ -47,12 +48,11 @@ def _rel(a, b, floor):
     return np.abs(a - b) / np.maximum(np.abs(b), floor)
 
 
-@pytest.mark.parametrize("use_fwd", [False, True])
-def test_adjoint_matches_oracle_analytic_small(use_fwd):
-    sc = scenes.make_object_scene(3000, 3)
-    K = 16
+def _check_against_analytic(sc, K, use_fwd, label):
+    """Every parameter's gradient of sum_r w_r T_r (seeded w) against the
+    oracle's analytic FP64 gradient over all n*K rays."""
     dirs = scenes.fibonacci_dirs(K, True)
-    n = 3000
+    n = int(np.asarray(sc["mean"]).shape[0])
     rays = np.arange(n * K, dtype=np.int64)
     orc = oracle.trace_rays(sc, dirs, 1, rays)
     rng = np.random.default_rng(42)
@@ -62,6 +62,8 @@ def test_adjoint_matches_oracle_analytic_small(use_fwd):
     ref = oracle.grad_rays(sc, dirs, 1, rays, w)
     sens = oracle.grad_rays(sc, dirs, 1, rays, w, absolute=2)
     go, gm, gl = _gpu_grads(sc, dirs, NO_EXIT, grad_ray=w.reshape(n, K), use_fwd=use_fwd)
+    print(f"[adjoint {label}] hits per ray {orc['n_incl'].mean():.2f}, rays carrying a gradient "
+          f"{np.count_nonzero(w) / w.size:.1%}", flush=True)
     for name, got, exp in (("opacity", go, ref["opacity"]), ("mean", gm, ref["mean"]),
                            ("log_scale", gl, ref["log_scale"])):
         rms = float(np.sqrt(np.mean(exp ** 2)))
@@ -73,11 +75,28 @@ def test_adjoint_matches_oracle_analytic_small(use_fwd):
         # (test_oracle_adjoint_pins.py)
         tol = 1e-3 * np.maximum(np.abs(exp), 1e-3 * rms) + KAPPA_G * sens[name]
         err = _rel(got.astype(np.float64), exp, 1e-3 * rms)
-        print(f"[adjoint small {name}] rms {rms:.3e} rel err max {err.max():.2e} p50 {np.median(err):.2e} "
+        print(f"[adjoint {label} {name}] rms {rms:.3e} rel err max {err.max():.2e} p50 {np.median(err):.2e} "
               f"p99 {np.quantile(err, 0.99):.2e}; max diff/tol {np.max(diff / tol):.3f}", flush=True)
         assert np.all(diff <= tol), name
         assert np.median(err) <= 1e-4
         assert rms > 0
+
+
+@pytest.mark.parametrize("use_fwd", [False, True])
+def test_adjoint_matches_oracle_analytic_small(use_fwd):
+    _check_against_analytic(scenes.make_object_scene(3000, 3), 16, use_fwd, "small")
+
+
+def test_adjoint_table_overflow_matches_oracle_analytic():
+    """The small scene with every Gaussian six times larger: a block's 1,024
+    rays (64 adjacent origins x 16 directions) meet 803 distinct Gaussians on
+    average and up to 1,448 (counted with the oracle), more than the block's
+    gradient table of 1,024 slots takes, so hits overflow into the block's
+    records and are summed in the second table pass; every parameter is still
+    checked against the oracle."""
+    sc = dict(scenes.make_object_scene(3000, 3))
+    sc["log_scale"] = (np.asarray(sc["log_scale"], np.float64) + math.log(6.0)).astype(np.float32)
+    _check_against_analytic(sc, 16, True, "dense")
 
 
 def test_adjoint_mean_gradient_path_and_autograd():
