@@ -207,3 +207,31 @@ def test_binary32_adjoint_deviation_within_the_sensitivity_bound(kind, n, K):
     # the bound is an error scale, not a loose ceiling: the measured deviation
     # reaches a visible fraction of it on some element
     assert max(worst.values()) > 0.01
+
+
+def test_dense_scene_overflows_the_adjoint_block_tables():
+    """The premise of the GPU test on the dense scene (the small object scene
+    with every Gaussian six times larger): a block of the adjoint traces 64
+    Gaussians adjacent in Morton order times all 16 directions, and such
+    blocks meet more distinct Gaussians than the 1,024 slots of the block's
+    gradient table. Counted with the oracle's exact inclusion test (no early
+    exit), blocks taken from the oracle's own Morton keys and stable sort."""
+    sc = dict(scenes.make_object_scene(3000, 3))
+    sc["log_scale"] = (np.asarray(sc["log_scale"], np.float64) + np.log(6.0)).astype(np.float32)
+    K, n = 16, 3000
+    dirs = scenes.fibonacci_dirs(K, True)
+    rays = np.arange(n * K, dtype=np.int64)
+    inc = np.zeros((n, n * K), dtype=bool)
+    for j in range(n):
+        inc[j] = oracle.pair_terms(sc, dirs, 1, rays, j)["inc"] > 0
+    _, _, keys = oracle.morton63(np.asarray(sc["mean"], np.float32))
+    perm = oracle.sort_keys(keys)
+    distinct = []
+    for m0 in range(0, n, 64):
+        orig = perm[m0:m0 + 64]
+        r = (orig[:, None] * K + np.arange(K)[None, :]).reshape(-1)
+        distinct.append(int(inc[:, r].any(axis=1).sum()))
+    distinct = np.array(distinct)
+    assert distinct.max() > 1024
+    assert (distinct > 1024).sum() >= 5
+    assert distinct.mean() > 700
